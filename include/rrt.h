@@ -1,0 +1,197 @@
+/*
+ * rrt.h -- run-time Haar-domain relighting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of librrt.so.  The operations follow the paper's statement of the
+ * problem (Alnasser & Foroosh, "Non-Linear Phase-Shifting of Haar Wavelets
+ * for Run-Time All-Frequency Lighting"): lighting and transport are
+ * represented by non-standard 2-D Haar coefficients (Sec. III, Sec. V.B);
+ * the lighting is rotated into each vertex's local frame directly in the
+ * Haar domain (Sec. V.A: the rotated map is g(w) = f(R w); Sec. V.B/V.C:
+ * coefficients of every coarser level follow from the finest one by
+ * 2x2 averaging and downsampling); outgoing radiance is the inner product of
+ * the rotated lighting with the vertex's transfer coefficients (Sec. III,
+ * transfer function; Sec. V.C, last algorithm step).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Data pointers are DEVICE pointers owned by the caller.  The library
+ *    never frees or retains them.  Host-side descriptor structs are read
+ *    during the call only.  Buffers must stay alive until the work queued
+ *    on `stream` has completed.
+ *  - Every call enqueues asynchronously on `stream` (a hipStream_t passed as
+ *    void*; NULL = the null stream) and returns a status: RRT_OK (0) or a
+ *    positive rrt_status.  Arguments are validated on the host before any
+ *    HIP call is made, so an error return means nothing was enqueued
+ *    (except RRT_ERR_DEVICE, reported when a launch itself fails).
+ *    rrt_last_error() returns a thread-local message for the last failure.
+ *    Nothing aborts and no exception crosses the ABI.
+ *  - Device-side data is never trusted for addressing: out-of-range indices
+ *    and malformed rotations give unspecified VALUES for the affected
+ *    results but never an out-of-bounds access.
+ *  - A cube map is [6][n][n] (row-major), n = 2^k with 1 <= n <= 1024
+ *    (the rotating calls, phase shift and relight, need n >= 2).  Faces 0..5 are +X,-X,+Y,-Y,+Z,-Z.
+ *    Texel (i, j) has U = 2j+1-n, V = 2i+1-n and centre direction
+ *      +X ( n,-V,-U)  -X (-n,-V, U)  +Y ( U, n, V)
+ *      -Y ( U,-n,-V)  +Z ( U,-V, n)  -Z (-U,-V,-n).
+ *  - Coefficients: orthonormal non-standard 2-D Haar of each face, Mallat
+ *    quadrant layout (S/H/V/D of a level in the top-left/top-right/
+ *    bottom-left/bottom-right quadrants of the current corner;
+ *    H = left-right, V = top-bottom, D = mixed, each /2 per 2x2 step).
+ *    The flat coefficient index is face*n*n + row*n + col (int32).
+ *  - A rotation is a row-major 3x3 float32 matrix R mapping local directions
+ *    to the lighting's frame; the rotated lighting is g(w) = L(R w), sampled
+ *    at texel centres with the nearest source texel.  R is quantised to
+ *    R_q = rint(R * 2^20) and the source texel is found in exact integer
+ *    arithmetic (major axis, ties to the lower axis; column
+ *    j' = min(n-1, floor(n (sc + |d_a|) / (2 |d_a|))), row likewise), so
+ *    results do not depend on floating-point evaluation order.
+ */
+#ifndef RRT_H
+#define RRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RRT_ABI_VERSION 1
+
+typedef enum {
+  RRT_OK = 0,
+  RRT_ERR_INVALID = 1,      /* bad argument (null pointer, size, alignment) */
+  RRT_ERR_UNSUPPORTED = 2,  /* valid but not implemented (dtype/size combination) */
+  RRT_ERR_WORKSPACE = 3,    /* workspace missing or smaller than *_workspace() reported */
+  RRT_ERR_DEVICE = 4        /* a HIP launch or runtime call failed */
+} rrt_status;
+
+typedef enum {
+  RRT_F32 = 0,   /* IEEE binary32 */
+  RRT_F16 = 1,   /* IEEE binary16 */
+  RRT_BF16 = 2,  /* bfloat16 (upper half of binary32) */
+  RRT_E4M3 = 3,  /* OCP FP8 E4M3FN (bias 7, max 448, no infinities) with
+                    one float32 scale per block of RRT_BLOCK values */
+  RRT_S16 = 4    /* int16 fixed point with one float32 scale per block of
+                    RRT_BLOCK values: value = code * scale */
+} rrt_dtype;
+
+/* Values per scale block of the block-scaled forms (RRT_E4M3, RRT_S16). */
+#define RRT_BLOCK 64
+
+/* Flags of rrt_relight. */
+#define RRT_COMPENSATED 1u  /* Neumaier-compensated accumulation of the dot */
+
+int rrt_abi_version(void);
+const char* rrt_status_string(int status);
+const char* rrt_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Haar transform of cube maps (representation, Sec. III / Sec. V.B).
+ *   pix, coef: [count][6][n][n] float32, may not overlap.
+ *   count >= 0 (0 = no-op), 1 <= n <= 1024, n a power of two.
+ *   No workspace: for n > 128 the work is split into 128 x 128 tiles plus
+ *   one coarse pass, and the tile sums between the two launches are staged
+ *   in the output buffer itself.
+ * --------------------------------------------------------------------- */
+int rrt_haar_forward(const float* pix, float* coef, int n, int64_t count, void* stream);
+int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t count, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Non-linear approximation (Sec. III, Haar-domain methods): keep the k
+ * entries of largest magnitude of each row.
+ *   x [rows][len] float32; idx [rows][k] int32 and val [rows][k] float32
+ *   receive the kept positions in ascending order and their values.
+ *   Ties in |x| go to the lower position.  NaN inputs: unspecified choice.
+ *   0 <= k <= len, len < 2^31.  Workspace: rrt_topk_workspace() bytes.
+ * --------------------------------------------------------------------- */
+int rrt_topk_workspace(int64_t rows, int64_t len, int k, size_t* bytes);
+int rrt_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val,
+             void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Dense Haar-domain rotation (the non-linear phase shift, Sec. V.A-V.C):
+ *   coef_out[r] = W S(R_r) W^T coef_in  for r < nrot.
+ *   coef_in [6][n][n], rot [nrot][9], coef_out [nrot][6][n][n] float32.
+ *   Workspace: rrt_haar_phase_shift_workspace() bytes (256-byte aligned).
+ * --------------------------------------------------------------------- */
+int rrt_haar_phase_shift_workspace(int n, int nrot, size_t* bytes);
+int rrt_haar_phase_shift(const float* coef_in, int n, const float* rot, int nrot,
+                         float* coef_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Relighting: radiance[f][v] = sum_k T_v[k] (W S(R_fv) W^T L)[k]
+ * (Sec. III transfer-function inner product with the lighting rotated into
+ * the vertex frame, Sec. V.A-V.C; rotate, recurse, integrate).
+ * --------------------------------------------------------------------- */
+typedef struct {
+  int n;                 /* face side, 2 <= n <= 1024, power of two */
+  int k;                 /* kept lighting coefficients, 1 <= k <= 6 n^2 */
+  const int32_t* idx;    /* [k] flat coefficient indices (any order; out-of-range
+                            entries ignored; duplicates: one of them wins) */
+  const void* val;       /* [k] values, dtype RRT_F32 or RRT_F16 */
+  int dtype;             /* rrt_dtype of val; RRT_F16 also stores the
+                            reconstructed source map in binary16 */
+} rrt_light;
+
+typedef struct {
+  int64_t nvert;         /* vertices V >= 0 */
+  int nnz;               /* coefficients per vertex, 1 <= nnz <= 6 n^2 */
+  const int32_t* idx;    /* [V][nnz] flat indices in the vertex's local frame,
+                            or NULL for dense rows (then nnz must be 6 n^2 and
+                            entry e is coefficient e); out-of-range ignored */
+  const void* val;       /* [V][nnz] values of dtype */
+  int dtype;             /* RRT_F32, RRT_BF16, RRT_E4M3 or RRT_S16 */
+  const float* block_scale; /* RRT_E4M3 / RRT_S16: [V][ceil(nnz/64)] scales,
+                            value = code * scale; otherwise ignored */
+} rrt_transport;
+
+typedef struct {
+  int nframes;           /* F >= 1 */
+  const float* frame_rot;/* [F][9] object rotations, or NULL (then F must be 1
+                            and R_v is used as is) */
+  const float* vert_rot; /* [V][9] vertex frames (local -> object) */
+} rrt_rotations;
+/* R_fv = (R_q(frame f) R_q(vertex v) + 2^19) >> 20, entry-wise in exact
+   integer arithmetic (flooring shift). */
+
+/* Workspace: the reconstructed source map (6 n^2 values, float32 or
+   binary16) plus a 6 n^2 float32 staging buffer, 256-byte aligned.  Only
+   L->n and L->dtype matter for its size. */
+int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
+                          unsigned flags, size_t* bytes);
+/* radiance: [F][V] float32 (frame-major).  Equivalent to
+   rrt_relight_prepare followed by rrt_relight_prepared. */
+int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
+                float* radiance, unsigned flags, void* ws, size_t ws_bytes, void* stream);
+
+/* The two halves of rrt_relight, for relighting many vertex batches or
+   frame sets under one lighting:
+   prepare  -- source reconstruction P = W^T L into the workspace (once per
+               lighting; Sec. V.B levels read in reverse);
+   prepared -- the per-vertex rotation and inner product reading P from a
+               workspace filled by prepare with the same L->n and L->dtype
+               (the workspace is only read, so several calls may share it). */
+int rrt_relight_prepare(const rrt_light* L, void* ws, size_t ws_bytes, void* stream);
+int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
+                         float* radiance, unsigned flags, const void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* ------------------------------------------------------------------------
+ * Storage conversion of coefficient values (reduced-precision forms).
+ *   src [rows][cols] float32 -> dst [rows][cols] of dtype:
+ *   RRT_F16, RRT_BF16: round to nearest even;
+ *   RRT_E4M3, RRT_S16: per block of RRT_BLOCK values of a row, with
+ *   m = max|x| of the block and M = 448 (E4M3) or 32767 (S16):
+ *   scale = m / M (1 if the block is all zero), stored in
+ *   block_scale [rows][ceil(cols/64)]; code = round-to-nearest-even of
+ *   x * (M / m), saturated to +-M.
+ * --------------------------------------------------------------------- */
+int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst,
+                float* block_scale, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RRT_H */

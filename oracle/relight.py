@@ -68,12 +68,16 @@ def phase_shift(coef, R):
 
 
 def relight(light_idx, light_val, n, vert_rot, frame_rot, t_idx, t_val,
-            vertices=None, frames=None):
+            vertices=None, frames=None, return_scale=False):
     """radiance[f][v] (FP64) for the selected frames x vertices.
 
     light_idx/light_val: stored lighting (values promoted to FP64 as stored).
     vert_rot [V, 3, 3], frame_rot [F, 3, 3] or None.
     t_idx [V, nnz] (None = dense, nnz = 6 n^2), t_val [V, nnz].
+    With return_scale, also returns sum_k |T_v[k] ghat[k]| per result: the
+    magnitude scale against which rounding errors of a finite-precision
+    evaluation of the same sum are measured (its ratio to |radiance| is the
+    condition number of the inner product).
     """
     V = np.asarray(vert_rot).shape[0]
     nf = 1 if frame_rot is None else np.asarray(frame_rot).shape[0]
@@ -81,6 +85,7 @@ def relight(light_idx, light_val, n, vert_rot, frame_rot, t_idx, t_val,
     frames = np.arange(nf) if frames is None else np.asarray(frames)
     P = reconstruct_lighting(light_idx, light_val, n)
     out = np.zeros((len(frames), len(vertices)), dtype=np.float64)
+    scale = np.zeros_like(out)
     for a, v in enumerate(vertices):
         T = np.zeros(6 * n * n, dtype=np.float64)
         vals = np.asarray(t_val[v], dtype=np.float64)
@@ -92,7 +97,8 @@ def relight(light_idx, light_val, n, vert_rot, frame_rot, t_idx, t_val,
             Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f)
             ghat = haar_forward(rotate_pixels(P, Rq)).ravel()
             out[b, a] = np.dot(T, ghat)
-    return out
+            scale[b, a] = np.dot(np.abs(T), np.abs(ghat))
+    return (out, scale) if return_scale else out
 
 
 def rel_l2(x, ref):

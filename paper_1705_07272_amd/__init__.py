@@ -1,0 +1,220 @@
+"""Run-time Haar-domain relighting on MI355X (gfx950).
+
+Thin torch-facing binding of librrt.so: every function checks and marshals
+its tensor arguments and calls the C ABI of include/rrt.h; all arithmetic
+runs in the library's HIP kernels.  torch provides device memory and the
+current stream only.
+"""
+import ctypes
+
+import torch
+
+from . import _abi
+from ._abi import (RRT_BF16, RRT_BLOCK, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
+                   RRT_S16, Light, RrtError, Rotations, Transport, check, lib)
+
+__all__ = ["haar_forward", "haar_inverse", "topk", "haar_phase_shift", "relight",
+           "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
+           "project_rows", "RrtError", "lib"]
+
+_DTYPES = {torch.float32: RRT_F32, torch.float16: RRT_F16, torch.bfloat16: RRT_BF16,
+           torch.uint8: RRT_E4M3, torch.int16: RRT_S16}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_or_null(t, name, dtype=None):
+    return ctypes.c_void_p(0) if t is None else _dev(t, name, dtype)
+
+
+def _workspace(nbytes, device):
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return ws
+
+
+def haar_forward(pix, out=None):
+    """Per-face Haar transform of cube maps [..., 6, n, n] (float32)."""
+    n = pix.shape[-1]
+    count = pix.numel() // (6 * n * n) if pix.numel() else 0
+    out = torch.empty_like(pix) if out is None else out
+    check(lib.rrt_haar_forward(_dev(pix, "pix", torch.float32), _dev(out, "out", torch.float32),
+                               n, count, _stream()))
+    return out
+
+
+def haar_inverse(coef, out=None):
+    n = coef.shape[-1]
+    count = coef.numel() // (6 * n * n) if coef.numel() else 0
+    out = torch.empty_like(coef) if out is None else out
+    check(lib.rrt_haar_inverse(_dev(coef, "coef", torch.float32), _dev(out, "out", torch.float32),
+                               n, count, _stream()))
+    return out
+
+
+def topk(x, k):
+    """Row-wise k largest |x| -> (idx int32 ascending, values) for x [rows, len]."""
+    rows, length = x.shape
+    idx = torch.empty((rows, k), dtype=torch.int32, device=x.device)
+    val = torch.empty((rows, k), dtype=torch.float32, device=x.device)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_topk_workspace(rows, length, k, ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, x.device)
+    check(lib.rrt_topk(_dev(x, "x", torch.float32), rows, length, k, _dev(idx, "idx"),
+                       _dev(val, "val"), _dev(ws, "ws"), nbytes.value, _stream()))
+    return idx, val
+
+
+def haar_phase_shift(coef, rot):
+    """Dense Haar-domain rotation of one cube map [6, n, n] by rot [r, 3, 3]."""
+    n = coef.shape[-1]
+    nrot = rot.shape[0]
+    out = torch.empty((nrot, 6, n, n), dtype=torch.float32, device=coef.device)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_haar_phase_shift_workspace(n, nrot, ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, coef.device)
+    check(lib.rrt_haar_phase_shift(_dev(coef, "coef", torch.float32), n,
+                                   _dev(rot, "rot", torch.float32), nrot,
+                                   _dev(out, "out"), _dev(ws, "ws"), nbytes.value, _stream()))
+    return out
+
+
+def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale):
+    L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
+              _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
+              _DTYPES[light_val.dtype])
+    nframes = 1 if frame_rot is None else frame_rot.shape[0]
+    R = Rotations(nframes, _ptr_or_null(frame_rot, "frame_rot", torch.float32).value,
+                  _dev(vert_rot, "vert_rot", torch.float32).value)
+    nvert = vert_rot.shape[0]
+    nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
+    T = Transport(nvert, nnz, _ptr_or_null(t_idx, "transport_idx", torch.int32).value,
+                  _dev(t_val, "transport_val",
+                       (torch.float32, torch.bfloat16, torch.uint8, torch.int16)).value,
+                  _DTYPES[t_val.dtype],
+                  _ptr_or_null(block_scale, "block_scale", torch.float32).value)
+    return L, R, T
+
+
+def relight_workspace_bytes(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None,
+                            block_scale=None, compensated=False):
+    L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
+                                    RRT_COMPENSATED if compensated else 0, ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
+            compensated=False, out=None, workspace=None):
+    """radiance [F, V] float32.
+
+    light_idx [k] int32, light_val [k] float32|float16; vert_rot [V, 3, 3]
+    float32; t_idx [V, nnz] int32 or None (dense rows); t_val [V, nnz]
+    float32|bfloat16|uint8 (E4M3 codes)|int16 (fixed-point codes), the
+    block-scaled forms with block_scale [V, ceil(nnz/64)];
+    frame_rot [F, 3, 3] float32 or None.
+    """
+    L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale)
+    flags = RRT_COMPENSATED if compensated else 0
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
+                                    ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _workspace(nbytes.value, vert_rot.device)
+    if out is None:
+        out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
+    check(lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
+                          _dev(out, "out", torch.float32), flags, _dev(workspace, "workspace"),
+                          workspace.numel(), _stream()))
+    return out
+
+
+class PreparedLighting:
+    """Lighting whose source map P = W^T L has been reconstructed into a
+    device workspace by rrt_relight_prepare."""
+
+    def __init__(self, n, light_idx, light_val, workspace):
+        self.n = n
+        self.light_idx = light_idx
+        self.light_val = light_val
+        self.workspace = workspace
+
+
+def prepare_lighting(n, light_idx, light_val, workspace=None):
+    L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
+              _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
+              _DTYPES[light_val.dtype])
+    nbytes = ctypes.c_size_t(0)
+    dummy_r = Rotations(1, None, 1)
+    dummy_t = Transport(0, 1, 1, 1, RRT_F32, None)
+    check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(dummy_r), ctypes.byref(dummy_t),
+                                    0, ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _workspace(nbytes.value, light_idx.device)
+    check(lib.rrt_relight_prepare(ctypes.byref(L), _dev(workspace, "workspace"), workspace.numel(),
+                                  _stream()))
+    return PreparedLighting(n, light_idx, light_val, workspace)
+
+
+def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
+                     compensated=False, out=None):
+    """relight() with a lighting already reconstructed by prepare_lighting()."""
+    L, R, T = _descriptors(prep.n, prep.light_idx, prep.light_val, vert_rot, t_idx, t_val,
+                           frame_rot, block_scale)
+    if out is None:
+        out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
+    check(lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
+                                   _dev(out, "out", torch.float32),
+                                   RRT_COMPENSATED if compensated else 0,
+                                   _dev(prep.workspace, "workspace"), prep.workspace.numel(),
+                                   _stream()))
+    return out
+
+
+def project_rows(pix, nnz):
+    """Haar transform of per-vertex pixel-domain transport [B, 6, n, n]
+    (float32, device) and its top-nnz truncation -> (idx [B, nnz] int32,
+    values [B, nnz] float32): the stored CSR rows of the relighting path."""
+    coef = haar_forward(pix)
+    return topk(coef.view(pix.shape[0], -1), nnz)
+
+
+def convert(x, dtype):
+    """Storage conversion of a [rows, cols] float32 tensor: 'f16', 'bf16',
+    'e4m3' or 's16' (the last two return (codes, block scales float32))."""
+    rows, cols = x.shape
+    if dtype == "f16":
+        out = torch.empty((rows, cols), dtype=torch.float16, device=x.device)
+        check(lib.rrt_convert(_dev(x, "x", torch.float32), rows, cols, RRT_F16, _dev(out, "out"),
+                              None, _stream()))
+        return out
+    if dtype == "bf16":
+        out = torch.empty((rows, cols), dtype=torch.bfloat16, device=x.device)
+        check(lib.rrt_convert(_dev(x, "x", torch.float32), rows, cols, RRT_BF16, _dev(out, "out"),
+                              None, _stream()))
+        return out
+    if dtype in ("e4m3", "s16"):
+        nblk = (cols + RRT_BLOCK - 1) // RRT_BLOCK
+        code_t, code = (torch.uint8, RRT_E4M3) if dtype == "e4m3" else (torch.int16, RRT_S16)
+        out = torch.empty((rows, cols), dtype=code_t, device=x.device)
+        scale = torch.empty((rows, nblk), dtype=torch.float32, device=x.device)
+        check(lib.rrt_convert(_dev(x, "x", torch.float32), rows, cols, code, _dev(out, "out"),
+                              _dev(scale, "scale"), _stream()))
+        return out, scale
+    raise ValueError(f"unknown dtype {dtype}")

@@ -1,0 +1,96 @@
+"""ctypes declarations of librrt.so (the C ABI of include/rrt.h).
+
+The library is loaded at import; a missing or unloadable library raises
+ImportError -- there is no fallback implementation.
+"""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librrt.so")
+
+RRT_OK = 0
+RRT_ERR_INVALID = 1
+RRT_ERR_UNSUPPORTED = 2
+RRT_ERR_WORKSPACE = 3
+RRT_ERR_DEVICE = 4
+
+RRT_F32 = 0
+RRT_F16 = 1
+RRT_BF16 = 2
+RRT_E4M3 = 3
+RRT_S16 = 4
+RRT_BLOCK = 64
+
+RRT_COMPENSATED = 1
+
+c_int = ctypes.c_int
+c_int64 = ctypes.c_int64
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+c_uint = ctypes.c_uint
+c_float = ctypes.c_float
+
+
+class Light(ctypes.Structure):
+    _fields_ = [("n", c_int), ("k", c_int), ("idx", c_void_p), ("val", c_void_p),
+                ("dtype", c_int)]
+
+
+class Transport(ctypes.Structure):
+    _fields_ = [("nvert", c_int64), ("nnz", c_int), ("idx", c_void_p), ("val", c_void_p),
+                ("dtype", c_int), ("block_scale", c_void_p)]
+
+
+class Rotations(ctypes.Structure):
+    _fields_ = [("nframes", c_int), ("frame_rot", c_void_p), ("vert_rot", c_void_p)]
+
+
+P = ctypes.POINTER
+
+SIGNATURES = {
+    "rrt_abi_version": (c_int, []),
+    "rrt_status_string": (ctypes.c_char_p, [c_int]),
+    "rrt_last_error": (ctypes.c_char_p, []),
+    "rrt_haar_forward": (c_int, [c_void_p, c_void_p, c_int, c_int64, c_void_p]),
+    "rrt_haar_inverse": (c_int, [c_void_p, c_void_p, c_int, c_int64, c_void_p]),
+    "rrt_topk_workspace": (c_int, [c_int64, c_int64, c_int, P(c_size_t)]),
+    "rrt_topk": (c_int, [c_void_p, c_int64, c_int64, c_int, c_void_p, c_void_p, c_void_p,
+                         c_size_t, c_void_p]),
+    "rrt_haar_phase_shift_workspace": (c_int, [c_int, c_int, P(c_size_t)]),
+    "rrt_haar_phase_shift": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p,
+                                     c_size_t, c_void_p]),
+    "rrt_relight_workspace": (c_int, [P(Light), P(Rotations), P(Transport), c_uint,
+                                      P(c_size_t)]),
+    "rrt_relight": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint, c_void_p,
+                            c_size_t, c_void_p]),
+    "rrt_relight_prepare": (c_int, [P(Light), c_void_p, c_size_t, c_void_p]),
+    "rrt_relight_prepared": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint,
+                                     c_void_p, c_size_t, c_void_p]),
+    "rrt_convert": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+}
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (run: python -m paper_1705_07272_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()
+
+
+class RrtError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def check(status):
+    if status != RRT_OK:
+        raise RrtError(status, lib.rrt_last_error().decode())
+    return status

@@ -1,0 +1,265 @@
+// Host side of the C ABI (include/rrt.h): argument validation (always
+// before any HIP call), workspace layout and dispatch to the kernels.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "rrt_internal.h"
+
+namespace rrt {
+
+static thread_local char g_last_error[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RRT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return RRT_OK;
+}
+
+static bool valid_n(int n, int lo) { return n >= lo && n <= 1024 && is_pow2(n); }
+
+// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float|half]
+struct RelightWs {
+  size_t dense_off, src_off, total;
+};
+
+static RelightWs relight_ws(int n, bool f16) {
+  const size_t cells = size_t(6) * n * n;
+  RelightWs w;
+  w.dense_off = 0;
+  w.src_off = align256(cells * sizeof(float));
+  w.total = w.src_off + align256(cells * (f16 ? sizeof(__half) : sizeof(float)));
+  return w;
+}
+
+static int validate_light(const rrt_light* L) {
+  if (!L) return fail(RRT_ERR_INVALID, "relight: null lighting descriptor");
+  if (!valid_n(L->n, 2)) return fail(RRT_ERR_INVALID, "relight: n=%d not a power of two in [2,1024]", L->n);
+  const int64_t cells = int64_t(6) * L->n * L->n;
+  if (L->k < 1 || L->k > cells) return fail(RRT_ERR_INVALID, "relight: light k=%d not in [1,%lld]", L->k, (long long)cells);
+  if (!L->idx || !L->val) return fail(RRT_ERR_INVALID, "relight: null lighting pointer");
+  if (L->dtype != RRT_F32 && L->dtype != RRT_F16)
+    return fail(RRT_ERR_UNSUPPORTED, "relight: lighting dtype %d (F32 or F16 only)", L->dtype);
+  return RRT_OK;
+}
+
+static int check_ws(const void* ws, size_t ws_bytes, size_t need, const char* what) {
+  if (!ws || ws_bytes < need)
+    return fail(RRT_ERR_WORKSPACE, "%s: workspace %zu < %zu bytes", what, ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(RRT_ERR_INVALID, "%s: workspace not 256-byte aligned", what);
+  return RRT_OK;
+}
+
+static int validate_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T) {
+  if (!L || !R || !T) return fail(RRT_ERR_INVALID, "relight: null descriptor");
+  const int vs = validate_light(L);
+  if (vs) return vs;
+  const int64_t cells = int64_t(6) * L->n * L->n;
+  if (R->nframes < 1) return fail(RRT_ERR_INVALID, "relight: nframes=%d < 1", R->nframes);
+  if (!R->frame_rot && R->nframes != 1)
+    return fail(RRT_ERR_INVALID, "relight: frame_rot is NULL but nframes=%d", R->nframes);
+  if (T->nvert < 0 || T->nvert > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "relight: nvert=%lld out of range", (long long)T->nvert);
+  if (T->nnz < 1 || T->nnz > cells) return fail(RRT_ERR_INVALID, "relight: nnz=%d not in [1,%lld]", T->nnz, (long long)cells);
+  if (!T->idx && T->nnz != cells)
+    return fail(RRT_ERR_INVALID, "relight: dense transport (idx NULL) needs nnz = 6 n^2 = %lld", (long long)cells);
+  if (T->nvert > 0 && (!T->val || !R->vert_rot))
+    return fail(RRT_ERR_INVALID, "relight: null transport values or vertex rotations");
+  if (T->dtype != RRT_F32 && T->dtype != RRT_BF16 && T->dtype != RRT_E4M3 && T->dtype != RRT_S16)
+    return fail(RRT_ERR_UNSUPPORTED, "relight: transport dtype %d (F32, BF16, E4M3 or S16)", T->dtype);
+  if ((T->dtype == RRT_E4M3 || T->dtype == RRT_S16) && !T->block_scale && T->nvert > 0)
+    return fail(RRT_ERR_INVALID, "relight: block-scaled transport needs block_scale");
+  if (int64_t(R->nframes) * T->nvert > (int64_t(1) << 40))
+    return fail(RRT_ERR_INVALID, "relight: output too large");
+  return RRT_OK;
+}
+
+}  // namespace rrt
+
+using namespace rrt;
+
+extern "C" {
+
+int rrt_abi_version(void) { return RRT_ABI_VERSION; }
+
+const char* rrt_status_string(int status) {
+  switch (status) {
+    case RRT_OK: return "ok";
+    case RRT_ERR_INVALID: return "invalid argument";
+    case RRT_ERR_UNSUPPORTED: return "unsupported";
+    case RRT_ERR_WORKSPACE: return "workspace too small";
+    case RRT_ERR_DEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+const char* rrt_last_error(void) { return g_last_error; }
+
+int rrt_haar_forward(const float* pix, float* coef, int n, int64_t count, void* stream) {
+  if (!valid_n(n, 1)) return fail(RRT_ERR_INVALID, "haar_forward: n=%d not a power of two in [1,1024]", n);
+  if (count < 0) return fail(RRT_ERR_INVALID, "haar_forward: count=%lld < 0", (long long)count);
+  if (count == 0) return RRT_OK;
+  if (!pix || !coef) return fail(RRT_ERR_INVALID, "haar_forward: null pointer");
+  if (pix == coef) return fail(RRT_ERR_INVALID, "haar_forward: in-place transform not supported");
+  if (count * 6 * (n / (n < 128 ? n : 128)) * (n / (n < 128 ? n : 128)) > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "haar_forward: count too large");
+  return launch_haar_forward(pix, coef, n, count, static_cast<hipStream_t>(stream));
+}
+
+int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t count, void* stream) {
+  if (!valid_n(n, 1)) return fail(RRT_ERR_INVALID, "haar_inverse: n=%d not a power of two in [1,1024]", n);
+  if (count < 0) return fail(RRT_ERR_INVALID, "haar_inverse: count=%lld < 0", (long long)count);
+  if (count == 0) return RRT_OK;
+  if (!pix || !coef) return fail(RRT_ERR_INVALID, "haar_inverse: null pointer");
+  if (pix == coef) return fail(RRT_ERR_INVALID, "haar_inverse: in-place transform not supported");
+  if (count * 6 * (n / (n < 128 ? n : 128)) * (n / (n < 128 ? n : 128)) > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "haar_inverse: count too large");
+  return launch_haar_inverse(coef, pix, n, count, static_cast<hipStream_t>(stream));
+}
+
+int rrt_topk_workspace(int64_t rows, int64_t len, int k, size_t* bytes) {
+  if (!bytes) return fail(RRT_ERR_INVALID, "topk_workspace: null bytes");
+  if (rows < 0 || len < 0 || k < 0 || k > len) return fail(RRT_ERR_INVALID, "topk_workspace: bad sizes");
+  *bytes = 0;
+  return RRT_OK;
+}
+
+int rrt_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val, void* ws,
+             size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (rows < 0 || rows > int64_t(0x7fffffff)) return fail(RRT_ERR_INVALID, "topk: rows=%lld out of range", (long long)rows);
+  if (len < 0 || len >= (int64_t(1) << 31)) return fail(RRT_ERR_INVALID, "topk: len=%lld out of range", (long long)len);
+  if (k < 0 || k > len) return fail(RRT_ERR_INVALID, "topk: k=%d not in [0,len=%lld]", k, (long long)len);
+  if (rows == 0 || k == 0) return RRT_OK;
+  if (!x || !idx || !val) return fail(RRT_ERR_INVALID, "topk: null pointer");
+  return launch_topk(x, rows, len, k, idx, val, static_cast<hipStream_t>(stream));
+}
+
+int rrt_haar_phase_shift_workspace(int n, int nrot, size_t* bytes) {
+  if (!bytes) return fail(RRT_ERR_INVALID, "phase_shift_workspace: null bytes");
+  if (!valid_n(n, 2) || nrot < 0) return fail(RRT_ERR_INVALID, "phase_shift_workspace: bad sizes");
+  const size_t cells = size_t(6) * n * n;
+  *bytes = align256(cells * sizeof(float)) + align256(cells * sizeof(float) * size_t(nrot));
+  return RRT_OK;
+}
+
+int rrt_haar_phase_shift(const float* coef_in, int n, const float* rot, int nrot, float* coef_out,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_n(n, 2)) return fail(RRT_ERR_INVALID, "phase_shift: n=%d not a power of two in [2,1024]", n);
+  if (nrot < 0 || nrot > 65535 || int64_t(nrot) * 6 * n * n > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "phase_shift: nrot=%d out of range", nrot);
+  if (nrot == 0) return RRT_OK;
+  if (!coef_in || !rot || !coef_out) return fail(RRT_ERR_INVALID, "phase_shift: null pointer");
+  size_t need = 0;
+  rrt_haar_phase_shift_workspace(n, nrot, &need);
+  if (!ws || ws_bytes < need)
+    return fail(RRT_ERR_WORKSPACE, "phase_shift: workspace %zu < %zu bytes", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(RRT_ERR_INVALID, "phase_shift: workspace not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t cells = size_t(6) * n * n;
+  float* pix = static_cast<float*>(ws);
+  float* rotated = reinterpret_cast<float*>(static_cast<char*>(ws) + align256(cells * sizeof(float)));
+  int st = launch_haar_inverse(coef_in, pix, n, 1, s);
+  if (st) return st;
+  st = launch_rotate_pixels(pix, rot, nrot, n, rotated, s);
+  if (st) return st;
+  return launch_haar_forward(rotated, coef_out, n, nrot, s);
+}
+
+int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
+                          unsigned flags, size_t* bytes) {
+  (void)flags;
+  if (!bytes) return fail(RRT_ERR_INVALID, "relight_workspace: null bytes");
+  const int st = validate_relight(L, R, T);
+  if (st) return st;
+  *bytes = relight_ws(L->n, L->dtype == RRT_F16).total;
+  return RRT_OK;
+}
+
+int rrt_relight_prepare(const rrt_light* L, void* ws, size_t ws_bytes, void* stream) {
+  int st = validate_light(L);
+  if (st) return st;
+  const bool f16 = L->dtype == RRT_F16;
+  const RelightWs w = relight_ws(L->n, f16);
+  st = check_ws(ws, ws_bytes, w.total, "relight_prepare");
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* dense = reinterpret_cast<float*>(base + w.dense_off);
+  void* src = base + w.src_off;
+  st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, dense, s);
+  if (st) return st;
+  if (f16) return launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, s);
+  return launch_haar_inverse(dense, static_cast<float*>(src), L->n, 1, s);
+}
+
+int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
+                         float* radiance, unsigned flags, const void* ws, size_t ws_bytes,
+                         void* stream) {
+  int st = validate_relight(L, R, T);
+  if (st) return st;
+  if (flags & ~RRT_COMPENSATED) return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
+  const bool f16 = L->dtype == RRT_F16;
+  const RelightWs w = relight_ws(L->n, f16);
+  st = check_ws(ws, ws_bytes, w.total, "relight");
+  if (st) return st;
+  if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight: null radiance");
+  if (T->nvert == 0) return RRT_OK;
+  RelightLaunch a;
+  a.src = static_cast<const char*>(ws) + w.src_off;
+  a.src_f16 = f16;
+  a.vert_rot = R->vert_rot;
+  a.frame_rot = R->frame_rot;
+  a.t_idx = T->idx;
+  a.t_val = T->val;
+  a.t_scale = T->block_scale;
+  a.t_dtype = T->dtype;
+  a.nnz = T->nnz;
+  a.nvert = T->nvert;
+  a.nframes = R->nframes;
+  a.n = L->n;
+  a.flags = flags;
+  a.out = radiance;
+  return launch_relight(a, static_cast<hipStream_t>(stream));
+}
+
+int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T, float* radiance,
+                unsigned flags, void* ws, size_t ws_bytes, void* stream) {
+  // validate everything before enqueueing anything
+  int st = validate_relight(L, R, T);
+  if (st) return st;
+  if (flags & ~RRT_COMPENSATED) return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
+  st = check_ws(ws, ws_bytes, relight_ws(L->n, L->dtype == RRT_F16).total, "relight");
+  if (st) return st;
+  if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight: null radiance");
+  st = rrt_relight_prepare(L, ws, ws_bytes, stream);
+  if (st) return st;
+  return rrt_relight_prepared(L, R, T, radiance, flags, ws, ws_bytes, stream);
+}
+
+int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst, float* block_scale,
+                void* stream) {
+  if (rows < 0 || cols < 0) return fail(RRT_ERR_INVALID, "convert: negative size");
+  if (dtype != RRT_F16 && dtype != RRT_BF16 && dtype != RRT_E4M3 && dtype != RRT_S16)
+    return fail(RRT_ERR_UNSUPPORTED, "convert: dtype %d (F16, BF16, E4M3 or S16)", dtype);
+  if (rows * int64_t(cols) > (int64_t(1) << 40)) return fail(RRT_ERR_INVALID, "convert: too large");
+  if (rows == 0 || cols == 0) return RRT_OK;
+  if (!src || !dst) return fail(RRT_ERR_INVALID, "convert: null pointer");
+  if ((dtype == RRT_E4M3 || dtype == RRT_S16) && !block_scale)
+    return fail(RRT_ERR_INVALID, "convert: block-scaled dtype needs block_scale");
+  return launch_convert(src, rows, cols, dtype, dst, block_scale, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Exact integer geometry of the cube-map rotation g(w) = f(R w)
+// (Sec. V.A: each point p of the rotated map takes the value of the original
+// at R p).  Device-side helpers shared by the relight and phase-shift
+// kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rrt {
+
+constexpr int kScaleBits = 20;  // R_q = rint(R * 2^20)
+
+// Quantised rotation, row-major int32.
+struct IRot {
+  int m[9];
+};
+
+__device__ __forceinline__ int quantise_entry(float r) {
+  return int(rintf(r * float(1 << kScaleBits)));
+}
+
+// R_fv = (R_q(frame) R_q(vertex) + 2^19) >> 20 (flooring shift), or R_q(vertex).
+__device__ __forceinline__ IRot frame_vertex_rotation(const float* __restrict__ vrot,
+                                                      const float* __restrict__ frot) {
+  IRot v, out;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v.m[k] = quantise_entry(vrot[k]);
+  if (frot == nullptr) return v;
+  int f[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) f[k] = quantise_entry(frot[k]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      int64_t acc = int64_t(1) << (kScaleBits - 1);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) acc += int64_t(f[3 * i + m]) * int64_t(v.m[3 * m + j]);
+      out.m[3 * i + j] = int(acc >> kScaleBits);
+    }
+  return out;
+}
+
+// Face axes: texel direction = U * eU + V * eV + n * eN with
+// faces +X,-X,+Y,-Y,+Z,-Z:
+//   +X ( n,-V,-U)  -X (-n,-V, U)  +Y ( U, n, V)
+//   -Y ( U,-n,-V)  +Z ( U,-V, n)  -Z (-U,-V,-n).
+// Each axis is a signed unit vector: encoded as axis index and sign.
+struct FaceAxes {
+  int3 mU, mV, mN;  // R * eU, R * eV, R * eN
+};
+
+__device__ __forceinline__ int pick3(int a, int b, int c, int axis) {
+  return axis == 0 ? a : (axis == 1 ? b : c);
+}
+
+// sign * (column `axis` of R), without dynamic register indexing.
+__device__ __forceinline__ int3 signed_column(const IRot& R, int axis, int sign) {
+  return make_int3(sign * pick3(R.m[0], R.m[1], R.m[2], axis),
+                   sign * pick3(R.m[3], R.m[4], R.m[5], axis),
+                   sign * pick3(R.m[6], R.m[7], R.m[8], axis));
+}
+
+__device__ __forceinline__ FaceAxes face_axes(const IRot& R, int face) {
+  // (axis, sign) of eU, eV, eN per face
+  const int uax = (face < 2) ? 2 : 0;
+  const int usg = (face == 0 || face == 5) ? -1 : 1;
+  const int vax = (face == 2 || face == 3) ? 2 : 1;
+  const int vsg = (face == 2) ? 1 : -1;
+  const int nax = face >> 1;
+  const int nsg = (face & 1) ? -1 : 1;
+  FaceAxes a;
+  a.mU = signed_column(R, uax, usg);
+  a.mV = signed_column(R, vax, vsg);
+  a.mN = signed_column(R, nax, nsg);
+  return a;
+}
+
+// Modular int32 arithmetic: the true direction components fit in int32 for
+// n <= 1024 (|R_q| <= 2^20, |dir| <= n sqrt(3)), so wrapped partial sums still
+// give the exact final value.
+__device__ __forceinline__ int wrap_mad(int a, int b, int c) {
+  return int(unsigned(a) * unsigned(b) + unsigned(c));
+}
+
+// floor(s * 2^logh / D) for |s| <= D, D >= 1, exact.  The binary32 estimate
+// is within one of the exact quotient (|quotient| <= 2^logh <= 512 and the
+// estimate's relative error is below 2^-21); the int64 test fixes it.
+__device__ __forceinline__ int floor_scaled_div(int s, int D, float h_over_D, int logh) {
+  int q = int(floorf(float(s) * h_over_D));
+  const int64_t num = int64_t(s) * (int64_t(1) << logh);
+  const int64_t lo = int64_t(q) * int64_t(D);
+  q -= int(lo > num);
+  q += int(lo + D <= num);
+  return q;
+}
+
+// Flat source texel (face * n^2 + i * n + j) of the integer direction d.
+// Major axis with ties to the lower axis; in-face coordinates
+//   +X (-z,-y)  -X (z,-y)  +Y (x, z)  -Y (x,-z)  +Z (x,-y)  -Z (-x,-y);
+// column j = min(n-1, h + floor(h sc / D)), h = n / 2, D = |d_a|.
+// Every output lies in [0, 6 n^2) whatever d is.
+__device__ __forceinline__ int source_texel(int x, int y, int z, int logn) {
+  const int n = 1 << logn;
+  const int logh = logn - 1;
+  const int ax = abs(x), ay = abs(y), az = abs(z);
+  const bool px = (ax >= ay) && (ax >= az);
+  const bool py = !px && (ay >= az);
+  const int da = px ? x : (py ? y : z);
+  int D = px ? ax : (py ? ay : az);
+  D = D > 0 ? D : 1;
+  const bool neg = da < 0;
+  const int face = 2 * (px ? 0 : (py ? 1 : 2)) + int(neg);
+  const int sc = px ? (neg ? z : -z) : (py ? x : (neg ? -x : x));
+  const int tc = py ? (neg ? -z : z) : -y;
+  const float hr = float(1 << logh) * __builtin_amdgcn_rcpf(float(D));
+  int j = (1 << logh) + floor_scaled_div(sc, D, hr, logh);
+  int i = (1 << logh) + floor_scaled_div(tc, D, hr, logh);
+  j = min(max(j, 0), n - 1);
+  i = min(max(i, 0), n - 1);
+  return (face << (2 * logn)) + (i << logn) + j;
+}
+
+}  // namespace rrt

@@ -1,0 +1,66 @@
+// Internal declarations shared by the host entry points and the kernels of
+// librrt.so.  Not part of the public ABI (see include/rrt.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rrt.h"
+
+namespace rrt {
+
+// Records a message for rrt_last_error() and returns `status`.
+int fail(int status, const char* fmt, ...);
+// Maps the last HIP error of a launch to RRT_ERR_DEVICE (or RRT_OK).
+int check_launch(const char* what);
+
+inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+inline int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Haar transform launchers (haar.hip).
+int launch_haar_forward(const float* pix, float* coef, int n, int64_t count, hipStream_t s);
+int launch_haar_inverse(const float* coef, float* pix, int n, int64_t count, hipStream_t s);
+// Inverse transform writing binary16 pixels (source map of the F16 form).
+int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n,
+                            hipStream_t s);
+
+// Selection (topk.hip).
+int launch_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val,
+                hipStream_t s);
+
+// Coefficient scatter into a zeroed dense map (relight.hip).
+int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n,
+                         float* dense, hipStream_t s);
+// Pixel-domain rotation of one map for a batch of rotations (relight.hip).
+int launch_rotate_pixels(const float* src, const float* rot, int nrot, int n, float* dst,
+                         hipStream_t s);
+
+struct RelightLaunch {
+  const void* src;          // [6][n][n] float32 or binary16 source map
+  bool src_f16;
+  const float* vert_rot;    // [V][9]
+  const float* frame_rot;   // [F][9] or nullptr
+  const int32_t* t_idx;     // [V][nnz] or nullptr (dense)
+  const void* t_val;        // [V][nnz]
+  const float* t_scale;     // [V][nblk] (E4M3) or nullptr
+  int t_dtype;
+  int nnz;
+  int64_t nvert;
+  int nframes;
+  int n;
+  unsigned flags;
+  float* out;               // [F][V]
+};
+int launch_relight(const RelightLaunch& a, hipStream_t s);
+
+// Storage conversion (convert.hip).
+int launch_convert(const float* src, int64_t rows, int cols, int dtype, void* dst,
+                   float* scale, hipStream_t s);
+
+}  // namespace rrt

@@ -1,0 +1,64 @@
+"""Test-case assembly: seeded scene data (scenes) turned into the stored
+inputs of the relighting path by the FP64 checker (oracle), plus the
+checker's reference radiance.  Used by the GPU parity tests and smoke().
+"""
+import numpy as np
+
+from oracle.haar import haar_forward
+from oracle.relight import lighting_coefficients, relight, rel_l2, transport_rows  # noqa: F401
+from scenes.scene import (Workload, frame_rotations, lighting_pixels, phong_exponents,
+                          transport_pixels, vertex_rotations)
+
+
+def workload(cfg, n, k_light, nverts, nnz, nframes=1, exp_lo=1.0, exp_hi=200.0,
+             vertex_frames="random"):
+    return Workload(cfg, f"test{cfg}", n, k_light, nverts, nframes, nnz, exp_lo, exp_hi,
+                    vertex_frames)
+
+
+def stored_transport(w, vertex_ids, batch=64):
+    """Checker-made transport rows of the given vertices: (idx int32 [B, nnz]
+    or None when dense, values float32 [B, nnz])."""
+    exps = phong_exponents(w)
+    vertex_ids = np.asarray(vertex_ids)
+    dense = w.nnz == 6 * w.n * w.n
+    idx_parts, val_parts = [], []
+    for s in range(0, len(vertex_ids), batch):
+        vids = vertex_ids[s:s + batch]
+        T = transport_pixels(w, exps[vids], vids)
+        if dense:
+            val_parts.append(haar_forward(T).reshape(len(vids), -1).astype(np.float32))
+        else:
+            i, v = transport_rows(T, w.nnz)
+            idx_parts.append(i)
+            val_parts.append(v)
+    vals = np.concatenate(val_parts) if val_parts else np.zeros((0, w.nnz), np.float32)
+    if dense:
+        return None, vals
+    idx = np.concatenate(idx_parts) if idx_parts else np.zeros((0, w.nnz), np.int32)
+    return idx, vals
+
+
+def build_case(w, vertex_ids=None):
+    """All stored inputs of a workload (for the listed vertices, default all)."""
+    vertex_ids = np.arange(w.nverts) if vertex_ids is None else np.asarray(vertex_ids)
+    pix = lighting_pixels(w.cfg, w.n)
+    li, lv = lighting_coefficients(pix, w.k_light)
+    Rv = vertex_rotations(w)[vertex_ids]
+    Rf = frame_rotations(w)
+    ti, tv = stored_transport(w, vertex_ids)
+    return dict(n=w.n, pix=pix, light_idx=li, light_val=lv, vert_rot=Rv, frame_rot=Rf,
+                t_idx=ti, t_val=tv)
+
+
+def reference(case, vertices=None, frames=None, return_scale=False):
+    return relight(case["light_idx"], case["light_val"], case["n"], case["vert_rot"],
+                   case["frame_rot"], case["t_idx"], case["t_val"], vertices=vertices,
+                   frames=frames, return_scale=return_scale)
+
+
+def frame_errors(got, ref):
+    """Per-frame relative L2 error of [F, V] radiance."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return [rel_l2(got[f], ref[f]) for f in range(ref.shape[0])]

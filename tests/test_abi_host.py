@@ -1,0 +1,148 @@
+"""The C ABI on the host (no GPU needed): librrt.so loads, exports every
+symbol include/rrt.h declares, and rejects bad arguments before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rrt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rrt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def rrt():
+    import paper_1705_07272_amd as m
+    return m
+
+
+def test_exports_every_declared_symbol(rrt):
+    syms = _declared_symbols()
+    assert len(syms) >= 12
+    raw = ctypes.CDLL(rrt._abi.LIB_PATH)
+    for s in syms:
+        assert hasattr(raw, s), s
+    assert set(syms) == set(rrt._abi.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_strings(rrt):
+    lib = rrt.lib
+    assert lib.rrt_abi_version() == 1
+    assert lib.rrt_status_string(0) == b"ok"
+    assert lib.rrt_status_string(3) == b"workspace too small"
+    assert lib.rrt_status_string(99) == b"unknown status"
+
+
+def _p(x):
+    return ctypes.c_void_p(x)
+
+
+def test_haar_validation(rrt):
+    lib = rrt.lib
+    E = rrt._abi
+    assert lib.rrt_haar_forward(_p(8), _p(16), 3, 1, None) == E.RRT_ERR_INVALID
+    assert b"power of two" in lib.rrt_last_error()
+    assert lib.rrt_haar_forward(_p(8), _p(16), 2048, 1, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_haar_forward(_p(8), _p(16), 8, -1, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_haar_forward(_p(0), _p(16), 8, 1, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_haar_forward(_p(16), _p(16), 8, 1, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_haar_forward(_p(0), _p(0), 8, 0, None) == E.RRT_OK          # empty: no-op
+    assert lib.rrt_haar_inverse(_p(8), _p(16), 0, 1, None) == E.RRT_ERR_INVALID
+
+
+def test_topk_validation(rrt):
+    lib = rrt.lib
+    E = rrt._abi
+    nb = ctypes.c_size_t(7)
+    assert lib.rrt_topk_workspace(1, 10, 3, ctypes.byref(nb)) == E.RRT_OK and nb.value == 0
+    assert lib.rrt_topk_workspace(1, 10, 11, ctypes.byref(nb)) == E.RRT_ERR_INVALID
+    assert lib.rrt_topk(_p(8), 1, 10, 11, _p(8), _p(8), None, 0, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_topk(_p(0), 1, 10, 3, _p(8), _p(8), None, 0, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_topk(_p(0), 0, 10, 3, _p(0), _p(0), None, 0, None) == E.RRT_OK
+    assert lib.rrt_topk(_p(0), 4, 10, 0, _p(0), _p(0), None, 0, None) == E.RRT_OK
+
+
+def test_phase_shift_validation(rrt):
+    lib = rrt.lib
+    E = rrt._abi
+    nb = ctypes.c_size_t(0)
+    assert lib.rrt_haar_phase_shift_workspace(8, 3, ctypes.byref(nb)) == E.RRT_OK
+    assert nb.value >= 4 * 6 * 64 * 4
+    assert lib.rrt_haar_phase_shift_workspace(1, 3, ctypes.byref(nb)) == E.RRT_ERR_INVALID
+    assert lib.rrt_haar_phase_shift(_p(8), 8, _p(8), 3, _p(8), _p(256), 16, None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_haar_phase_shift(_p(8), 8, _p(8), 3, _p(8), _p(0), 1 << 20, None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_haar_phase_shift(_p(8), 8, _p(8), 3, _p(8), _p(257), 1 << 20, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_haar_phase_shift(_p(8), 8, _p(8), 70000, _p(8), _p(256), 1 << 30, None) == E.RRT_ERR_INVALID
+
+
+def _desc(rrt, n=8, k=10, nframes=1, frame_rot=0, nvert=5, nnz=16, tidx=8, tval=8,
+          tdtype=0, ldtype=0, scale=0):
+    E = rrt._abi
+    L = E.Light(n, k, 8, 8, ldtype)
+    R = E.Rotations(nframes, frame_rot, 8)
+    T = E.Transport(nvert, nnz, tidx, tval, tdtype, scale)
+    return L, R, T
+
+
+def _relight_ws(rrt, L, R, T, flags=0):
+    nb = ctypes.c_size_t(0)
+    st = rrt.lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
+                                       ctypes.byref(nb))
+    return st, nb.value
+
+
+def test_relight_validation(rrt):
+    E = rrt._abi
+    st, nb = _relight_ws(rrt, *_desc(rrt))
+    assert st == E.RRT_OK and nb == 256 * ((6 * 64 * 4 + 255) // 256) * 2
+    st16, nb16 = _relight_ws(rrt, *_desc(rrt, ldtype=E.RRT_F16))
+    assert st16 == E.RRT_OK and nb16 < nb
+    cases = [
+        (dict(n=3), E.RRT_ERR_INVALID),
+        (dict(n=1), E.RRT_ERR_INVALID),
+        (dict(k=0), E.RRT_ERR_INVALID),
+        (dict(k=6 * 64 + 1), E.RRT_ERR_INVALID),
+        (dict(nframes=0), E.RRT_ERR_INVALID),
+        (dict(nframes=2), E.RRT_ERR_INVALID),                  # no frame rotations
+        (dict(nnz=0), E.RRT_ERR_INVALID),
+        (dict(tidx=0, nnz=16), E.RRT_ERR_INVALID),             # dense needs nnz = 6 n^2
+        (dict(tdtype=E.RRT_F16), E.RRT_ERR_UNSUPPORTED),
+        (dict(ldtype=E.RRT_BF16), E.RRT_ERR_UNSUPPORTED),
+        (dict(tdtype=E.RRT_E4M3), E.RRT_ERR_INVALID),          # needs block scales
+        (dict(tdtype=E.RRT_S16), E.RRT_ERR_INVALID),
+        (dict(tdtype=7), E.RRT_ERR_UNSUPPORTED),
+        (dict(nvert=-1), E.RRT_ERR_INVALID),
+        (dict(tval=0), E.RRT_ERR_INVALID),
+    ]
+    for kw, want in cases:
+        st, _ = _relight_ws(rrt, *_desc(rrt, **kw))
+        assert st == want, (kw, st, rrt.lib.rrt_last_error())
+    assert _relight_ws(rrt, *_desc(rrt, tidx=0, nnz=6 * 64))[0] == E.RRT_OK
+    assert _relight_ws(rrt, *_desc(rrt, tdtype=E.RRT_E4M3, scale=8))[0] == E.RRT_OK
+    assert _relight_ws(rrt, *_desc(rrt, tdtype=E.RRT_S16, scale=8))[0] == E.RRT_OK
+    L, R, T = _desc(rrt)
+    lib = rrt.lib
+    assert lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8), 0, _p(256),
+                           16, None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8), 4, _p(256),
+                           1 << 20, None) == E.RRT_ERR_INVALID                 # unknown flag
+    assert lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(0), 0, _p(256),
+                           1 << 20, None) == E.RRT_ERR_INVALID                 # null radiance
+    assert lib.rrt_relight(None, ctypes.byref(R), ctypes.byref(T), _p(8), 0, _p(256), 1 << 20,
+                           None) == E.RRT_ERR_INVALID
+
+
+def test_convert_validation(rrt):
+    lib = rrt.lib
+    E = rrt._abi
+    assert lib.rrt_convert(_p(8), 2, 3, E.RRT_F32, _p(8), None, None) == E.RRT_ERR_UNSUPPORTED
+    assert lib.rrt_convert(_p(8), 2, 3, E.RRT_E4M3, _p(8), None, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_convert(_p(8), 2, 3, E.RRT_S16, _p(8), None, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_convert(_p(0), 2, 3, E.RRT_BF16, _p(8), None, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_convert(_p(0), 0, 3, E.RRT_BF16, _p(0), None, None) == E.RRT_OK

@@ -1,0 +1,138 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (one relight launch over every vertex), on outputs the FP64
+checker can afford: all of them for the 1,000-vertex dense scene, a sample
+(including the last vertices of the grid) for the 50,000-vertex scenes.
+
+Rows of sampled vertices are made by the checker (scene pixels -> FP64 Haar
+-> top-256); the other rows only fill the launch and are projected on the
+device.  The checker never sees a device-made value.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_07272_amd as m
+    return m
+
+
+def _device_rows(rrt, w, batch=2048):
+    from scenes.scene import phong_exponents, transport_pixels_torch
+    exps = phong_exponents(w)
+    idx = torch.empty((w.nverts, w.nnz), dtype=torch.int32, device="cuda")
+    val = torch.empty((w.nverts, w.nnz), dtype=torch.float32, device="cuda")
+    for s in range(0, w.nverts, batch):
+        e = min(w.nverts, s + batch)
+        T = transport_pixels_torch(w, exps[s:e], np.arange(s, e), "cuda", dtype=torch.float32)
+        i, v = rrt.project_rows(T.contiguous(), w.nnz)
+        idx[s:e] = i
+        val[s:e] = v
+    return idx, val
+
+
+def _sample(nverts, count, seed):
+    rng = np.random.default_rng(seed)
+    mid = rng.choice(np.arange(4, nverts - 4), size=count - 8, replace=False)
+    return np.sort(np.concatenate([np.arange(4), mid, np.arange(nverts - 4, nverts)]))
+
+
+def test_full_dense_n32_all_vertices(rrt):
+    """1,000 vertices, dense 6x32x32 lighting and transport, every output."""
+    from cases import build_case, frame_errors, reference
+    from scenes.scene import WORKLOADS
+    w = WORKLOADS[1]
+    case = build_case(w)
+    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
+                      torch.from_numpy(case["light_val"]).cuda(),
+                      torch.from_numpy(case["vert_rot"]).cuda(), None,
+                      torch.from_numpy(case["t_val"]).cuda())
+    torch.cuda.synchronize()
+    ref = reference(case)
+    err = max(frame_errors(out.cpu().numpy(), ref))
+    print(f"dense n=32 V=1000 rel-L2 {err:.3e}")
+    assert err <= 1e-5
+
+
+def _full_case(rrt, cfg, sample_count, seed):
+    from cases import stored_transport
+    from oracle.relight import lighting_coefficients
+    from scenes.scene import WORKLOADS, frame_rotations, lighting_pixels, vertex_rotations
+    w = WORKLOADS[cfg]
+    li, lv = lighting_coefficients(lighting_pixels(cfg, w.n), w.k_light)
+    rot = vertex_rotations(w)
+    frot = frame_rotations(w)
+    sample = _sample(w.nverts, sample_count, seed)
+    s_idx, s_val = stored_transport(w, sample)
+    idx, val = _device_rows(rrt, w)
+    idx[torch.from_numpy(sample).cuda().long()] = torch.from_numpy(s_idx).cuda()
+    val[torch.from_numpy(sample).cuda().long()] = torch.from_numpy(s_val).cuda()
+    case = dict(n=w.n, light_idx=li, light_val=lv, vert_rot=rot[sample], frame_rot=frot,
+                t_idx=s_idx, t_val=s_val)
+    return w, case, sample, rot, frot, idx, val
+
+
+def test_full_cube128_v50000_plain_f32(rrt):
+    """6x128^2, top-1024 lighting, 50,000 vertices, CSR-256 FP32: sampled
+    outputs of the full launch against the checker, rel-L2 <= 1e-5."""
+    from cases import frame_errors, reference
+    w, case, sample, rot, frot, idx, val = _full_case(rrt, 2, 40, 1)
+    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
+                      torch.from_numpy(case["light_val"]).cuda(), torch.from_numpy(rot).cuda(),
+                      idx, val)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[:, sample]
+    err = max(frame_errors(got, reference(case)))
+    print(f"cube128 V=50000 sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def frames_case(rrt):
+    return _full_case(rrt, 3, 16, 2)
+
+
+def _frames_run(rrt, frames_case, form):
+    from cases import frame_errors, reference
+    w, case, sample, rot, frot, idx, val = frames_case
+    scale = None
+    if form == "bf16":
+        tval = rrt.convert(val, "bf16")
+    else:
+        tval, scale = rrt.convert(val, form)
+    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
+                      torch.from_numpy(case["light_val"]).cuda().half(),
+                      torch.from_numpy(rot).cuda(), idx, tval, block_scale=scale,
+                      frame_rot=torch.from_numpy(frot).cuda(), compensated=True)
+    torch.cuda.synchronize()
+    if "ref" not in case:
+        case["ref"] = reference(case)
+    errs = frame_errors(out.cpu().numpy()[:, sample], case["ref"])
+    print(f"cube128 V=50000 F=64 {form} transport + f16 lighting: max frame rel-L2 {max(errs):.3e}")
+    return max(errs)
+
+
+def test_full_cube128_v50000_f64frames_s16_f16(rrt, frames_case):
+    """Same scene, 64 frames, block-scaled int16 transport + FP16 lighting,
+    compensated FP32 accumulation: every frame's rel-L2 <= 1e-3 against the
+    FP64 checker on the FP32 stored inputs."""
+    assert _frames_run(rrt, frames_case, "s16") <= 1e-3
+
+
+def test_full_cube128_v50000_f64frames_bf16_f16(rrt, frames_case):
+    """BF16 transport: its 8-bit significand alone costs 1.6e-3 rel-L2 on
+    this scene even in exact arithmetic (pinned on the CPU by
+    test_storage_forms_exact_arithmetic), so the bound here is the format's:
+    <= 2.5e-3 (BF16 storage plus FP16 lighting plus FP32 evaluation)."""
+    assert _frames_run(rrt, frames_case, "bf16") <= 2.5e-3
+
+
+def test_full_cube128_v50000_f64frames_e4m3_f16(rrt, frames_case):
+    """E4M3 transport with 64-value block scales: 3-bit significand, about
+    2e-2 rel-L2 from storage alone (CPU pin); bound 3e-2."""
+    assert _frames_run(rrt, frames_case, "e4m3") <= 3e-2

@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 checker.
+
+Tolerances of the FP32 path:
+  * workload-shaped cases (the paper-style scenes: n >= 32, Phong transport,
+    HDR lighting): rel-L2 per frame <= 1e-5 against the FP64 checker on the
+    same stored inputs;
+  * every element (all cases): |got - ref| <= 1e-5 |ref| + 2e-7 s, where
+    s = sum_k |T_k ghat_k| is the checker's magnitude scale of the inner
+    product.  2e-7 is about 3.4 binary32 unit roundoffs: the FP32 pipeline
+    (reconstruction, gather, 2x2 levels, products, tree sum) perturbs each
+    term by a few roundoffs, so ill-conditioned tiny cases (cancelling terms,
+    s >> |ref|) are judged against s instead of |ref|.
+Integer work (selection indices, storage codes) is compared bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_07272_amd as m
+    return m
+
+
+def dev(x, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def check_frames(got, ref_scale, tol=TOL_F32, rel_l2=True):
+    """ref_scale = (reference [F, V], magnitude scale [F, V])."""
+    from cases import frame_errors
+    ref, scale = ref_scale
+    got = np.asarray(got, np.float64)
+    bound = 1e-5 * np.abs(ref) + 2e-7 * scale
+    worst = np.max(np.abs(got - ref) - bound) if ref.size else -1.0
+    assert worst <= 0.0, (np.abs(got - ref) / np.maximum(bound, 1e-300)).max()
+    errs = frame_errors(got, ref) if ref.size else [0.0]
+    if rel_l2:
+        assert max(errs) <= tol, errs
+    return max(errs)
+
+
+# ---------------------------------------------------------------- Haar (a1, a3)
+@pytest.mark.parametrize("n,count", [(1, 2), (2, 3), (8, 1), (32, 2), (128, 1), (256, 2), (512, 1)])
+def test_haar_forward_inverse(rrt, n, count):
+    from oracle.haar import haar_forward, haar_inverse
+    rng = np.random.default_rng(n + count)
+    x = rng.normal(size=(count, 6, n, n)).astype(np.float32)
+    got = rrt.haar_forward(dev(x)).cpu().numpy()
+    ref = haar_forward(x.astype(np.float64))
+    assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
+    back = rrt.haar_inverse(dev(got)).cpu().numpy()
+    ref_back = haar_inverse(got.astype(np.float64))
+    assert np.linalg.norm(back - ref_back) <= 1e-6 * np.linalg.norm(ref_back)
+
+
+# ---------------------------------------------------------------- selection (a2)
+@pytest.mark.parametrize("rows,length,k", [(1, 1, 1), (3, 5, 2), (2, 1000, 7), (4, 1025, 1025),
+                                           (1, 98304, 1024), (5, 6144, 256), (2, 3000, 0)])
+def test_topk_exact(rrt, rows, length, k):
+    from oracle.select import topk_abs
+    rng = np.random.default_rng(rows * 7 + length)
+    x = rng.normal(size=(rows, length)).astype(np.float32)
+    x[:, ::3] = np.round(x[:, ::3] * 2)          # many exact ties, signed zeros
+    if length > 10:
+        x[0, 5] = -0.0
+    idx, val = rrt.topk(dev(x), k)
+    idx, val = idx.cpu().numpy(), val.cpu().numpy()
+    for r in range(rows):
+        want = topk_abs(x[r], k)
+        assert idx[r].tolist() == want.tolist()
+        assert np.array_equal(val[r].view(np.uint32), x[r][want].view(np.uint32))
+
+
+# ---------------------------------------------------------------- storage forms (a7)
+def test_convert_bf16_f16(rrt):
+    rng = np.random.default_rng(3)
+    x = (rng.normal(size=(37, 300)) * np.exp(rng.normal(size=(37, 300)) * 4)).astype(np.float32)
+    t = dev(x)
+    assert torch.equal(rrt.convert(t, "bf16").view(torch.int16), t.to(torch.bfloat16).view(torch.int16))
+    assert torch.equal(rrt.convert(t, "f16").view(torch.int16), t.to(torch.float16).view(torch.int16))
+
+
+def test_convert_e4m3(rrt):
+    rng = np.random.default_rng(4)
+    cols = 300                                    # ragged last block
+    x = (rng.normal(size=(9, cols)) * np.exp(rng.normal(size=(9, cols)) * 3)).astype(np.float32)
+    x[2, :64] = 0.0                               # all-zero block -> scale 1
+    codes, scale = rrt.convert(dev(x), "e4m3")
+    codes, scale = codes.cpu(), scale.cpu().numpy()
+    nblk = (cols + 63) // 64
+    for r in range(9):
+        for b in range(nblk):
+            blk = x[r, b * 64:(b + 1) * 64]
+            amax = np.float32(np.max(np.abs(blk)))
+            inv = np.float32(448.0) / amax if amax > 0 else np.float32(1.0)
+            sc = amax / np.float32(448.0) if amax > 0 else np.float32(1.0)
+            assert scale[r, b] == sc
+            want = torch.from_numpy((blk * inv).astype(np.float32)).to(torch.float8_e4m3fn)
+            assert torch.equal(codes[r, b * 64:(b + 1) * 64], want.view(torch.uint8)), (r, b)
+
+
+def test_convert_s16(rrt):
+    rng = np.random.default_rng(5)
+    cols = 200
+    x = (rng.normal(size=(7, cols)) * np.exp(rng.normal(size=(7, cols)) * 3)).astype(np.float32)
+    x[1, 64:128] = 0.0
+    codes, scale = rrt.convert(dev(x), "s16")
+    codes, scale = codes.cpu().numpy(), scale.cpu().numpy()
+    for r in range(7):
+        for b in range((cols + 63) // 64):
+            blk = x[r, b * 64:(b + 1) * 64]
+            amax = np.float32(np.max(np.abs(blk)))
+            inv = np.float32(32767.0) / amax if amax > 0 else np.float32(1.0)
+            sc = amax / np.float32(32767.0) if amax > 0 else np.float32(1.0)
+            assert scale[r, b] == sc
+            want = np.clip(np.rint(blk * inv), -32767, 32767).astype(np.int16)
+            assert np.array_equal(codes[r, b * 64:(b + 1) * 64], want), (r, b)
+
+
+# ---------------------------------------------------------------- dense phase shift (a4+a5)
+@pytest.mark.parametrize("n", [2, 4, 8, 32, 256])
+def test_phase_shift(rrt, n):
+    from oracle.relight import phase_shift
+    from scenes.scene import random_rotations
+    rng = np.random.default_rng(n)
+    coef = rng.normal(size=(6, n, n)).astype(np.float32)
+    rots = list(random_rotations(50 + n, 3))
+    rots.append(np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], np.float32))
+    c, s = np.cos(np.pi / 4), np.sin(np.pi / 4)
+    rots.append(np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]], np.float32))
+    R = np.stack(rots).astype(np.float32)
+    got = rrt.haar_phase_shift(dev(coef), dev(R)).cpu().numpy()
+    for r in range(len(R)):
+        ref = phase_shift(coef.astype(np.float64), R[r])
+        assert np.linalg.norm(got[r] - ref) <= 2e-6 * np.linalg.norm(ref), r
+
+
+# ---------------------------------------------------------------- relight (a3-a6)
+def run_relight(rrt, case, **kw):
+    out = rrt.relight(case["n"], dev(case["light_idx"]), dev(case["light_val"]),
+                      dev(case["vert_rot"]), None if case["t_idx"] is None else dev(case["t_idx"]),
+                      dev(case["t_val"]),
+                      frame_rot=None if case["frame_rot"] is None else dev(case["frame_rot"]), **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("compensated", [False, True])
+def test_relight_dense_n32(rrt, compensated):
+    """Dense transport and dense lighting at n = 32, 67 vertices (ragged)."""
+    from cases import build_case, reference, workload
+    w = workload(101, 32, 6 * 32 * 32, 67, 6 * 32 * 32, exp_lo=1.0, exp_hi=64.0,
+                 vertex_frames="normals")
+    case = build_case(w)
+    got = run_relight(rrt, case, compensated=compensated)
+    check_frames(got, reference(case, return_scale=True))
+
+
+@pytest.mark.parametrize("n,k,nnz,V", [(2, 24, 24, 5), (4, 40, 17, 9), (8, 100, 64, 33),
+                                       (16, 300, 128, 20), (64, 1024, 256, 21),
+                                       (128, 1024, 256, 41)])
+def test_relight_sparse(rrt, n, k, nnz, V):
+    from cases import build_case, reference, workload
+    w = workload(200 + n, n, k, V, nnz, exp_lo=1.0, exp_hi=200.0)
+    case = build_case(w)
+    check_frames(run_relight(rrt, case), reference(case, return_scale=True), rel_l2=n >= 32)
+
+
+def test_relight_frames_composition(rrt):
+    """Frame rotations composed with vertex frames (fixed-point rule)."""
+    from cases import build_case, reference, workload
+    w = workload(301, 32, 512, 13, 256, nframes=5)
+    case = build_case(w)
+    check_frames(run_relight(rrt, case), reference(case, return_scale=True))
+
+
+def test_relight_n256_regions(rrt):
+    """n = 256: four 128 x 128 regions per face and the levels above them."""
+    from cases import build_case, reference, workload
+    w = workload(302, 256, 2048, 6, 256, exp_lo=1.0, exp_hi=8.0)   # low exponents: 5 faces
+    case = build_case(w)
+    assert len(np.unique(case["t_idx"] // (256 * 256))) > 1
+    check_frames(run_relight(rrt, case), reference(case, return_scale=True))
+
+
+def test_relight_edge_cases(rrt):
+    from cases import build_case, reference, workload
+    w = workload(303, 16, 64, 4, 32)
+    case = build_case(w)
+    # empty vertex set: nothing to do, no error
+    empty = dict(case, vert_rot=case["vert_rot"][:0], t_idx=case["t_idx"][:0], t_val=case["t_val"][:0])
+    assert run_relight(rrt, empty).shape == (1, 0)
+    # single coefficient, single light coefficient
+    one = dict(case, light_idx=case["light_idx"][:1], light_val=case["light_val"][:1],
+               t_idx=case["t_idx"][:, :1].copy(), t_val=case["t_val"][:, :1].copy())
+    check_frames(run_relight(rrt, one), reference(one, return_scale=True), rel_l2=False)
+    # out-of-range transport indices are ignored
+    bad = dict(case, t_idx=case["t_idx"].copy())
+    bad["t_idx"][:, 3] = -5
+    bad["t_idx"][:, 7] = 6 * 16 * 16 + 2
+    ok = dict(case, t_val=case["t_val"].copy())
+    ok["t_val"][:, [3, 7]] = 0.0
+    check_frames(run_relight(rrt, bad), reference(ok, return_scale=True), rel_l2=False)
+
+
+def test_relight_identity_and_constant(rrt):
+    """Closed forms: identity rotation = plain inner product; constant
+    lighting c -> n c sum_F T[DC_F]."""
+    from cases import build_case, workload
+    n = 32
+    w = workload(304, n, 6, 8, 200)
+    case = build_case(w)
+    L = np.zeros(6 * n * n)
+    L[case["light_idx"]] = case["light_val"]
+    const = dict(case, light_idx=np.arange(6, dtype=np.int32) * n * n,
+                 light_val=np.full(6, n * 2.0, np.float32))
+    got = run_relight(rrt, const)[0]
+    for v in range(8):
+        full = np.zeros(6 * n * n)
+        full[case["t_idx"][v]] = case["t_val"][v]
+        assert abs(got[v] - 2.0 * n * sum(full[f * n * n] for f in range(6))) <= 1e-5 * abs(got[v])
+    ident = dict(case, vert_rot=np.tile(np.eye(3, dtype=np.float32), (8, 1, 1)))
+    got = run_relight(rrt, ident)[0]
+    for v in range(8):
+        ref = np.dot(case["t_val"][v].astype(np.float64), L[case["t_idx"][v]])
+        assert abs(got[v] - ref) <= 1e-5 * abs(ref)
+
+
+def test_relight_workspace_reuse_and_determinism(rrt):
+    from cases import build_case, workload
+    w = workload(305, 64, 512, 30, 256)
+    case = build_case(w)
+    a = run_relight(rrt, case)
+    b = run_relight(rrt, case)
+    assert np.array_equal(a, b)
