@@ -26,7 +26,7 @@ PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.32 T non-packed 32-bit lane-o
 PEAK_HBM_GBS = 8000.0
 # Algorithmic 32-bit operations per rotated texel (exact integer source map
 # plus gather plus its share of the 2x2 levels); derivation in the design doc.
-OPS_PER_TEXEL = 32
+OPS_PER_TEXEL = 36
 
 KERNEL_SOURCES = ["paper_1705_07272_amd/csrc/relight.hip", "paper_1705_07272_amd/csrc/geometry.h"]
 

@@ -1,6 +1,7 @@
 """Builds librrt.so (all HIP kernels and the C ABI) in-tree for gfx950.
 
-Usage: python -m paper_1705_07272_amd.build   (or build() from Python)
+Usage: python paper_1705_07272_amd/build.py   (standalone: importing the
+package itself needs the built library)
 """
 import glob
 import os

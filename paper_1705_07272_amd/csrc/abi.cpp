@@ -72,7 +72,7 @@ static int validate_relight(const rrt_light* L, const rrt_rotations* R, const rr
   if (T->nvert < 0 || T->nvert > int64_t(0x7fffffff))
     return fail(RRT_ERR_INVALID, "relight: nvert=%lld out of range", (long long)T->nvert);
   if (T->nnz < 1 || T->nnz > cells) return fail(RRT_ERR_INVALID, "relight: nnz=%d not in [1,%lld]", T->nnz, (long long)cells);
-  if (!T->idx && T->nnz != cells)
+  if (T->nvert > 0 && !T->idx && T->nnz != cells)
     return fail(RRT_ERR_INVALID, "relight: dense transport (idx NULL) needs nnz = 6 n^2 = %lld", (long long)cells);
   if (T->nvert > 0 && (!T->val || !R->vert_rot))
     return fail(RRT_ERR_INVALID, "relight: null transport values or vertex rotations");

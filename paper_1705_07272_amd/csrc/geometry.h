@@ -84,42 +84,62 @@ __device__ __forceinline__ int wrap_mad(int a, int b, int c) {
   return int(unsigned(a) * unsigned(b) + unsigned(c));
 }
 
-// floor(s * 2^logh / D) for |s| <= D, D >= 1, exact.  The binary32 estimate
-// is within one of the exact quotient (|quotient| <= 2^logh <= 512 and the
-// estimate's relative error is below 2^-21); the int64 test fixes it.
-__device__ __forceinline__ int floor_scaled_div(int s, int D, float h_over_D, int logh) {
-  int q = int(floorf(float(s) * h_over_D));
+// floor(s * 2^logh / D) exactly, given q0 within one of it (|s| <= D, D >= 1):
+// one int64 comparison on each side.
+__device__ __forceinline__ int exact_floor(int s, int D, int logh, int q0) {
   const int64_t num = int64_t(s) * (int64_t(1) << logh);
-  const int64_t lo = int64_t(q) * int64_t(D);
-  q -= int(lo > num);
-  q += int(lo + D <= num);
-  return q;
+  const int64_t lo = int64_t(q0) * int64_t(D);
+  q0 -= int(lo > num);
+  q0 += int(lo + D <= num);
+  return q0;
 }
 
 // Flat source texel (face * n^2 + i * n + j) of the integer direction d.
-// Major axis with ties to the lower axis; in-face coordinates
-//   +X (-z,-y)  -X (z,-y)  +Y (x, z)  -Y (x,-z)  +Z (x,-y)  -Z (-x,-y);
-// column j = min(n-1, h + floor(h sc / D)), h = n / 2, D = |d_a|.
-// Every output lies in [0, 6 n^2) whatever d is.
-__device__ __forceinline__ int source_texel(int x, int y, int z, int logn) {
+// Major axis a = argmax |d_k| with ties to the lower axis, face 2a + [d_a < 0],
+// in-face coordinates
+//   +X (-z,-y)  -X (z,-y)  +Y (x, z)  -Y (x,-z)  +Z (x,-y)  -Z (-x,-y),
+// column j = min(n-1, h + floor(h sc / D)), h = n / 2, D = |d_a|; row i
+// likewise from tc.
+//
+// The quotient h sc / D (|.| <= h) is estimated in binary32: float(sc) and
+// the product each round once (2^-24), v_rcp_f32 is within one ulp (2^-23),
+// so the estimate is within h 2^-22 of the exact value.  When its fractional
+// part is at least eps = h 2^-20 away from an integer the floor is exact;
+// otherwise (rare) the int64 test decides.  Every output is in [0, 6 n^2)
+// for any proper rotation; malformed input only yields some other index.
+__device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
   const int n = 1 << logn;
   const int logh = logn - 1;
-  const int ax = abs(x), ay = abs(y), az = abs(z);
-  const bool px = (ax >= ay) && (ax >= az);
+  const int h = 1 << logh;
+  const int nx = -x, ny = -y, nz = -z;
+  const int ax = max(x, nx), ay = max(y, ny), az = max(z, nz);
+  const bool px = ax >= max(ay, az);
   const bool py = !px && (ay >= az);
+  const int D = max(max(max(ax, ay), az), 1);
   const int da = px ? x : (py ? y : z);
-  int D = px ? ax : (py ? ay : az);
-  D = D > 0 ? D : 1;
   const bool neg = da < 0;
-  const int face = 2 * (px ? 0 : (py ? 1 : 2)) + int(neg);
-  const int sc = px ? (neg ? z : -z) : (py ? x : (neg ? -x : x));
-  const int tc = py ? (neg ? -z : z) : -y;
-  const float hr = float(1 << logh) * __builtin_amdgcn_rcpf(float(D));
-  int j = (1 << logh) + floor_scaled_div(sc, D, hr, logh);
-  int i = (1 << logh) + floor_scaled_div(tc, D, hr, logh);
-  j = min(max(j, 0), n - 1);
-  i = min(max(i, 0), n - 1);
+  const int face = (px ? 0 : (py ? 2 : 4)) + int(neg);
+  const int t1 = neg ? z : nz;
+  const int t2 = neg ? nx : x;
+  const int sc = px ? t1 : (py ? x : t2);
+  const int tc = py ? (neg ? nz : z) : ny;
+  const float hr = float(h) * __builtin_amdgcn_rcpf(float(D));
+  const float qs = float(sc) * hr, qt = float(tc) * hr;
+  const float fs = floorf(qs), ft = floorf(qt);
+  int j = int(fs), i = int(ft);
+  const float es = qs - fs, et = qt - ft;
+  if (fminf(fminf(es, 1.0f - es), fminf(et, 1.0f - et)) < eps) {
+    j = exact_floor(sc, D, logh, j);
+    i = exact_floor(tc, D, logh, i);
+  }
+  j = min(h + j, n - 1);
+  i = min(h + i, n - 1);
   return (face << (2 * logn)) + (i << logn) + j;
+}
+
+// Margin of the binary32 quotient estimate (see source_texel).
+__device__ __forceinline__ float quotient_margin(int logn) {
+  return float(1 << (logn - 1)) * 0x1p-20f;
 }
 
 }  // namespace rrt

@@ -34,15 +34,27 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Gathers from the source map go through a raw buffer resource: 32-bit
+// offsets (no 64-bit address arithmetic per texel) and hardware range
+// checking (reads past the map return 0).
+constexpr int kBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+
 template <typename SrcT>
-__device__ __forceinline__ float load_src(const SrcT* p, int i);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const SrcT* p, int count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<SrcT*>(p), short(0),
+                                           count * int(sizeof(SrcT)), kBufferWord3);
+}
+
+template <typename SrcT>
+__device__ __forceinline__ float load_src(__amdgpu_buffer_rsrc_t r, int i);
 template <>
-__device__ __forceinline__ float load_src<float>(const float* p, int i) {
-  return p[i];
+__device__ __forceinline__ float load_src<float>(__amdgpu_buffer_rsrc_t r, int i) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
 }
 template <>
-__device__ __forceinline__ float load_src<__half>(const __half* p, int i) {
-  return __half2float(p[i]);
+__device__ __forceinline__ float load_src<__half>(__amdgpu_buffer_rsrc_t r, int i) {
+  const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0);
+  return __half2float(__ushort_as_half(b));
 }
 
 // OCP E4M3FN: s eeee mmm, bias 7, subnormals, 0x7f/0xff NaN, no infinities.
@@ -170,7 +182,9 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   const int logn = p.logn;
   const int n = 1 << logn;
   const int G = n >> LOGQ;                // regions per face side
-  const SrcT* src = static_cast<const SrcT*>(p.src);
+  const __amdgpu_buffer_rsrc_t src =
+      source_resource(static_cast<const SrcT*>(p.src), 6 * (n << logn));
+  const float eps = quotient_margin(logn);
   const bool comp = p.comp != 0;
 
   // faces touched by this vertex's transport row
@@ -216,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             dz = wrap_mad(ax.mU.z, U0, dz);
 #pragma unroll
             for (int c = 0; c < T; ++c) {
-              g[r][c] = load_src<SrcT>(src, source_texel(dx, dy, dz, logn));
+              g[r][c] = load_src<SrcT>(src, source_texel(dx, dy, dz, logn, eps));
               dx = wrap_mad(ax.mU.x, 2, dx);
               dy = wrap_mad(ax.mU.y, 2, dy);
               dz = wrap_mad(ax.mU.z, 2, dz);
@@ -366,7 +380,7 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   const int dx = wrap_mad(ax.mU.x, U, wrap_mad(ax.mV.x, V, wrap_mad(ax.mN.x, n, 0)));
   const int dy = wrap_mad(ax.mU.y, U, wrap_mad(ax.mV.y, V, wrap_mad(ax.mN.y, n, 0)));
   const int dz = wrap_mad(ax.mU.z, U, wrap_mad(ax.mV.z, V, wrap_mad(ax.mN.z, n, 0)));
-  dst[int64_t(r) * 6 * per_face + q] = src[source_texel(dx, dy, dz, logn)];
+  dst[int64_t(r) * 6 * per_face + q] = src[source_texel(dx, dy, dz, logn, quotient_margin(logn))];
 }
 
 template <int Q, typename SrcT>

@@ -146,6 +146,30 @@ def test_phase_shift(rrt, n):
         assert np.linalg.norm(got[r] - ref) <= 2e-6 * np.linalg.norm(ref), r
 
 
+@pytest.mark.parametrize("n", [8, 32, 128])
+def test_phase_shift_index_map_exact(rrt, n):
+    """Rotating a texel-ID map (P[q] = q) through the public phase shift and
+    transforming back gives the source index of every texel: compared bit
+    for bit with the checker's integer map, for random, boundary-heavy
+    (45-degree, 22.5-degree) and cube-group rotations."""
+    from oracle.haar import haar_forward, haar_inverse
+    from oracle.sphere import quantise_rotation, source_index
+    from scenes.scene import random_rotations
+    ids = np.arange(6 * n * n, dtype=np.float64).reshape(6, n, n)
+    coef = haar_forward(ids).astype(np.float32)
+    rots = list(random_rotations(70 + n, 6))
+    for ang in (np.pi / 4, np.pi / 8):
+        c, s_ = np.cos(ang), np.sin(ang)
+        rots += [np.array([[1, 0, 0], [0, c, -s_], [0, s_, c]]), np.array([[c, 0, s_], [0, 1, 0], [-s_, 0, c]])]
+    rots.append(np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]]))
+    R = np.stack(rots).astype(np.float32)
+    out = rrt.haar_phase_shift(dev(coef), dev(R)).cpu().numpy().astype(np.float64)
+    for r in range(len(R)):
+        got = np.rint(haar_inverse(out[r])).astype(np.int64)
+        want = source_index(quantise_rotation(R[r]), n)
+        assert np.array_equal(got, want), (r, int((got != want).sum()))
+
+
 # ---------------------------------------------------------------- relight (a3-a6)
 def run_relight(rrt, case, **kw):
     out = rrt.relight(case["n"], dev(case["light_idx"]), dev(case["light_val"]),
