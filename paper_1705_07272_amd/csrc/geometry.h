@@ -98,13 +98,14 @@ __device__ __forceinline__ int exact_floor(int s, int D, int logh, int q0) {
 // Major axis a = argmax |d_k| with ties to the lower axis, face 2a + [d_a < 0],
 // in-face coordinates
 //   +X (-z,-y)  -X (z,-y)  +Y (x, z)  -Y (x,-z)  +Z (x,-y)  -Z (-x,-y),
-// column j = min(n-1, h + floor(h sc / D)), h = n / 2, D = |d_a|; row i
+// column j = min(n-1, floor(h (sc + D) / D)), h = n / 2, D = |d_a|; row i
 // likewise from tc.
 //
-// The quotient h sc / D (|.| <= h) is estimated in binary32: float(sc) and
-// the product each round once (2^-24), v_rcp_f32 is within one ulp (2^-23),
-// so the estimate is within h 2^-22 of the exact value.  When its fractional
-// part is at least eps = h 2^-20 away from an integer the floor is exact;
+// h (sc + D) / D = h sc / D + h (in [0, 2h]) is estimated in binary32 as
+// fma(float(sc), h rcp(D), h): float(sc) rounds once (2^-24), v_rcp_f32 is
+// within one ulp (2^-23), the fma rounds once (at most 2h 2^-24), so the
+// estimate is within h 2^-21 of the exact value.  When its fractional part
+// is at least eps = h 2^-19 away from an integer the floor is exact;
 // otherwise (rare) the int64 test decides.  Every output is in [0, 6 n^2)
 // for any proper rotation; malformed input only yields some other index.
 __device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
@@ -123,23 +124,25 @@ __device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float
   const int t2 = neg ? nx : x;
   const int sc = px ? t1 : (py ? x : t2);
   const int tc = py ? (neg ? nz : z) : ny;
-  const float hr = float(h) * __builtin_amdgcn_rcpf(float(D));
-  const float qs = float(sc) * hr, qt = float(tc) * hr;
+  const float hf = float(h);
+  const float hr = hf * __builtin_amdgcn_rcpf(float(D));
+  const float qs = __builtin_fmaf(float(sc), hr, hf);
+  const float qt = __builtin_fmaf(float(tc), hr, hf);
   const float fs = floorf(qs), ft = floorf(qt);
   int j = int(fs), i = int(ft);
   const float es = qs - fs, et = qt - ft;
   if (fminf(fminf(es, 1.0f - es), fminf(et, 1.0f - et)) < eps) {
-    j = exact_floor(sc, D, logh, j);
-    i = exact_floor(tc, D, logh, i);
+    j = h + exact_floor(sc, D, logh, j - h);
+    i = h + exact_floor(tc, D, logh, i - h);
   }
-  j = min(h + j, n - 1);
-  i = min(h + i, n - 1);
+  j = min(j, n - 1);
+  i = min(i, n - 1);
   return (face << (2 * logn)) + (i << logn) + j;
 }
 
 // Margin of the binary32 quotient estimate (see source_texel).
 __device__ __forceinline__ float quotient_margin(int logn) {
-  return float(1 << (logn - 1)) * 0x1p-20f;
+  return float(1 << (logn - 1)) * 0x1p-19f;
 }
 
 }  // namespace rrt

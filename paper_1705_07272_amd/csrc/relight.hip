@@ -13,7 +13,7 @@
 //
 // Work decomposition (one 256-thread workgroup per vertex, all frames):
 //   * only the faces touched by the vertex's transport row are processed;
-//   * a face is processed in Q x Q regions (Q = min(n, 128)); each of the
+//   * a face is processed in Q x Q regions (Q = min(n, 64)); each of the
 //     16 x 16 threads owns a T x T tile (T = Q / 16): it computes T^2 source
 //     indices (incremental along a row, d += 2 R e_U), gathers the source
 //     texels (L2-resident map) and runs the tile's levels in registers;
@@ -33,6 +33,11 @@ namespace rrt {
 namespace {
 
 constexpr int kThreads = 256;
+// Region side for large faces: a 64 x 64 region (16 KiB LDS image, 4 x 4
+// texels per thread) leaves room for five 256-thread workgroups per CU,
+// which hides the gather latency better than 128 x 128 regions (64 KiB,
+// two workgroups per CU); measured on MI355X at n = 128.
+constexpr int kMaxRegion = 64;
 
 // Gathers from the source map go through a raw buffer resource: 32-bit
 // offsets (no 64-bit address arithmetic per texel) and hardware range
@@ -391,14 +396,13 @@ int launch_q(const RelightParams& prm, int64_t nvert, hipStream_t s) {
 
 template <typename SrcT>
 int launch_src(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
-  switch (n < 128 ? n : 128) {
+  switch (n < kMaxRegion ? n : kMaxRegion) {
     case 2: return launch_q<2, SrcT>(prm, nvert, s);
     case 4: return launch_q<4, SrcT>(prm, nvert, s);
     case 8: return launch_q<8, SrcT>(prm, nvert, s);
     case 16: return launch_q<16, SrcT>(prm, nvert, s);
     case 32: return launch_q<32, SrcT>(prm, nvert, s);
-    case 64: return launch_q<64, SrcT>(prm, nvert, s);
-    default: return launch_q<128, SrcT>(prm, nvert, s);
+    default: return launch_q<kMaxRegion, SrcT>(prm, nvert, s);
   }
 }
 
