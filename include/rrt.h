@@ -144,6 +144,11 @@ typedef struct {
   int dtype;             /* RRT_F32, RRT_BF16, RRT_E4M3 or RRT_S16 */
   const float* block_scale; /* RRT_E4M3 / RRT_S16: [V][ceil(nnz/64)] scales,
                             value = code * scale; otherwise ignored */
+  const int32_t* cluster;   /* NULL, or [V] cluster of each vertex: then idx is a
+                            per-cluster support table [C][nnz] and vertex v uses
+                            row cluster[v] (values stay per vertex);
+                            out-of-range clusters contribute nothing */
+  int nclusters;            /* C when cluster != NULL */
 } rrt_transport;
 
 typedef struct {
@@ -189,6 +194,51 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
  * --------------------------------------------------------------------- */
 int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst,
                 float* block_scale, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned transport decoder (not part of the paper): an MLP maps a vertex's
+ * position and normal to its transport values on a per-cluster support.
+ *   encode:  gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7) of the 6
+ *            inputs (position scaled to [-1,1], unit normal), 102 features
+ *            zero-padded to RRT_MLP_IN, stored bfloat16 [B][128]; feature
+ *            order: the six inputs, then per band six sines, six cosines.
+ *   layers:  z = W a + b; gelu (tanh form) after each of the 4 hidden layers
+ *            of width 256; linear output layer of width 256.  Weights are
+ *            bfloat16, packed layer after layer, each [out][in] row-major
+ *            (RRT_MLP_WEIGHT_COUNT values); biases float32 packed likewise
+ *            (RRT_MLP_BIAS_COUNT).  Products accumulate in FP32 on the
+ *            matrix cores.
+ * --------------------------------------------------------------------- */
+#define RRT_MLP_IN 128
+#define RRT_MLP_HIDDEN 256
+#define RRT_MLP_OUT 256
+#define RRT_MLP_WEIGHTS 5
+#define RRT_MLP_WEIGHT_COUNT 294912
+#define RRT_MLP_BIAS_COUNT 1280
+
+/* pos_nrm [B][6] float32 -> x [B][128] bfloat16. */
+int rrt_mlp_encode(const float* pos_nrm, int64_t B, void* x, void* stream);
+/* Activation workspace for a batch of B rows (256-byte aligned). */
+int rrt_mlp_workspace(int64_t B, size_t* bytes);
+/* out [B][256] float32.  Keeps the activations of this batch in ws for a
+   following rrt_mlp_backward on the same batch. */
+int rrt_mlp_forward(const void* w, const float* bias, const void* x, int64_t B, float* out,
+                    void* ws, size_t ws_bytes, void* stream);
+/* Gradients of a scalar whose gradient with respect to out is dout [B][256]:
+   dw [RRT_MLP_WEIGHT_COUNT] (overwritten), db [RRT_MLP_BIAS_COUNT]
+   (overwritten).  ws must hold the activations of rrt_mlp_forward on the
+   same w, x and B. */
+int rrt_mlp_backward(const void* w, const void* x, int64_t B, const float* dout, float* dw,
+                     float* db, void* ws, size_t ws_bytes, void* stream);
+/* Mean squared error: dout = 2 (out - target) / count; *loss (a device
+   double) += sum (out - target)^2 / count. */
+int rrt_mse(const float* out, const float* target, int64_t count, float* dout, double* loss,
+            void* stream);
+/* One Adam step on n parameters (FP32 master, moments m and v); also writes
+   the bfloat16 copy when param_bf16 is not NULL.  step >= 1. */
+int rrt_adam_step(float* param, void* param_bf16, float* m, float* v, const float* grad,
+                  int64_t n, float lr, float beta1, float beta2, float eps, int step,
+                  void* stream);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,8 @@ from . import _abi
 from ._abi import (RRT_BF16, RRT_BLOCK, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
                    RRT_S16, Light, RrtError, Rotations, Transport, check, lib)
 
-__all__ = ["haar_forward", "haar_inverse", "topk", "haar_phase_shift", "relight",
+__all__ = ["haar_forward", "haar_inverse", "topk", "haar_phase_shift", "relight", "mlp_encode",
+           "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
 
@@ -94,7 +95,8 @@ def haar_phase_shift(coef, rot):
     return out
 
 
-def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale):
+def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
+                 cluster=None):
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -107,7 +109,9 @@ def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, blo
                   _dev(t_val, "transport_val",
                        (torch.float32, torch.bfloat16, torch.uint8, torch.int16)).value,
                   _DTYPES[t_val.dtype],
-                  _ptr_or_null(block_scale, "block_scale", torch.float32).value)
+                  _ptr_or_null(block_scale, "block_scale", torch.float32).value,
+                  _ptr_or_null(cluster, "cluster", torch.int32).value,
+                  0 if cluster is None else t_idx.shape[0])
     return L, R, T
 
 
@@ -121,16 +125,18 @@ def relight_workspace_bytes(n, light_idx, light_val, vert_rot, t_idx, t_val, fra
 
 
 def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
-            compensated=False, out=None, workspace=None):
+            compensated=False, out=None, workspace=None, cluster=None):
     """radiance [F, V] float32.
 
     light_idx [k] int32, light_val [k] float32|float16; vert_rot [V, 3, 3]
     float32; t_idx [V, nnz] int32 or None (dense rows); t_val [V, nnz]
     float32|bfloat16|uint8 (E4M3 codes)|int16 (fixed-point codes), the
     block-scaled forms with block_scale [V, ceil(nnz/64)];
-    frame_rot [F, 3, 3] float32 or None.
+    frame_rot [F, 3, 3] float32 or None.  With cluster [V] int32, t_idx is a
+    per-cluster support table [C, nnz] and vertex v uses row cluster[v].
     """
-    L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale)
+    L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
+                           cluster)
     flags = RRT_COMPENSATED if compensated else 0
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
@@ -162,7 +168,7 @@ def prepare_lighting(n, light_idx, light_val, workspace=None):
               _DTYPES[light_val.dtype])
     nbytes = ctypes.c_size_t(0)
     dummy_r = Rotations(1, None, 1)
-    dummy_t = Transport(0, 1, 1, 1, RRT_F32, None)
+    dummy_t = Transport(0, 1, 1, 1, RRT_F32, None, None, 0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(dummy_r), ctypes.byref(dummy_t),
                                     0, ctypes.byref(nbytes)))
     if workspace is None:
@@ -173,10 +179,10 @@ def prepare_lighting(n, light_idx, light_val, workspace=None):
 
 
 def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
-                     compensated=False, out=None):
+                     compensated=False, out=None, cluster=None):
     """relight() with a lighting already reconstructed by prepare_lighting()."""
     L, R, T = _descriptors(prep.n, prep.light_idx, prep.light_val, vert_rot, t_idx, t_val,
-                           frame_rot, block_scale)
+                           frame_rot, block_scale, cluster)
     if out is None:
         out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
     check(lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
@@ -218,3 +224,65 @@ def convert(x, dtype):
                               _dev(scale, "scale"), _stream()))
         return out, scale
     raise ValueError(f"unknown dtype {dtype}")
+
+
+# ---------------------------------------------------------------------------
+# Learned transport decoder
+# ---------------------------------------------------------------------------
+from ._abi import (RRT_MLP_BIAS_COUNT, RRT_MLP_HIDDEN, RRT_MLP_IN, RRT_MLP_OUT,  # noqa: E402,F401
+                   RRT_MLP_WEIGHT_COUNT)
+
+
+def mlp_encode(pos_nrm):
+    """[B, 6] float32 -> [B, 128] bfloat16 positional encoding."""
+    B = pos_nrm.shape[0]
+    x = torch.empty((B, RRT_MLP_IN), dtype=torch.bfloat16, device=pos_nrm.device)
+    check(lib.rrt_mlp_encode(_dev(pos_nrm, "pos_nrm", torch.float32), B, _dev(x, "x"), _stream()))
+    return x
+
+
+def mlp_workspace(B, device):
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_mlp_workspace(B, ctypes.byref(nbytes)))
+    return _workspace(nbytes.value, device)
+
+
+def mlp_forward(w_bf16, bias, x, workspace=None, out=None):
+    """out [B, 256] float32 for packed bfloat16 weights and float32 biases."""
+    B = x.shape[0]
+    workspace = mlp_workspace(B, x.device) if workspace is None else workspace
+    out = torch.empty((B, RRT_MLP_OUT), dtype=torch.float32, device=x.device) if out is None else out
+    check(lib.rrt_mlp_forward(_dev(w_bf16, "w", torch.bfloat16), _dev(bias, "bias", torch.float32),
+                              _dev(x, "x", torch.bfloat16), B, _dev(out, "out", torch.float32),
+                              _dev(workspace, "workspace"), workspace.numel(), _stream()))
+    return out
+
+
+def mlp_backward(w_bf16, x, dout, workspace, dw=None, db=None):
+    """(dw [294912], db [1280]) float32; workspace from the forward pass."""
+    B = x.shape[0]
+    dw = torch.empty(RRT_MLP_WEIGHT_COUNT, dtype=torch.float32, device=x.device) if dw is None else dw
+    db = torch.empty(RRT_MLP_BIAS_COUNT, dtype=torch.float32, device=x.device) if db is None else db
+    check(lib.rrt_mlp_backward(_dev(w_bf16, "w", torch.bfloat16), _dev(x, "x", torch.bfloat16), B,
+                               _dev(dout, "dout", torch.float32), _dev(dw, "dw", torch.float32),
+                               _dev(db, "db", torch.float32), _dev(workspace, "workspace"),
+                               workspace.numel(), _stream()))
+    return dw, db
+
+
+def mse(out, target, dout=None, loss=None):
+    """(dout, loss) with loss a device float64 scalar tensor (accumulated)."""
+    dout = torch.empty_like(out) if dout is None else dout
+    loss = torch.zeros((), dtype=torch.float64, device=out.device) if loss is None else loss
+    check(lib.rrt_mse(_dev(out, "out", torch.float32), _dev(target, "target", torch.float32),
+                      out.numel(), _dev(dout, "dout", torch.float32), _dev(loss, "loss", torch.float64),
+                      _stream()))
+    return dout, loss
+
+
+def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, param_bf16=None):
+    check(lib.rrt_adam_step(_dev(param, "param", torch.float32),
+                            _ptr_or_null(param_bf16, "param_bf16", torch.bfloat16),
+                            _dev(m, "m", torch.float32), _dev(v, "v", torch.float32),
+                            _dev(grad, "grad", torch.float32), param.numel(), lr, beta1, beta2,
+                            eps, step, _stream()))

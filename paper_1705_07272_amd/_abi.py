@@ -23,6 +23,13 @@ RRT_BLOCK = 64
 
 RRT_COMPENSATED = 1
 
+RRT_MLP_IN = 128
+RRT_MLP_HIDDEN = 256
+RRT_MLP_OUT = 256
+RRT_MLP_WEIGHTS = 5
+RRT_MLP_WEIGHT_COUNT = 294912
+RRT_MLP_BIAS_COUNT = 1280
+
 c_int = ctypes.c_int
 c_int64 = ctypes.c_int64
 c_size_t = ctypes.c_size_t
@@ -38,7 +45,8 @@ class Light(ctypes.Structure):
 
 class Transport(ctypes.Structure):
     _fields_ = [("nvert", c_int64), ("nnz", c_int), ("idx", c_void_p), ("val", c_void_p),
-                ("dtype", c_int), ("block_scale", c_void_p)]
+                ("dtype", c_int), ("block_scale", c_void_p), ("cluster", c_void_p),
+                ("nclusters", c_int)]
 
 
 class Rotations(ctypes.Structure):
@@ -67,6 +75,16 @@ SIGNATURES = {
     "rrt_relight_prepared": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint,
                                      c_void_p, c_size_t, c_void_p]),
     "rrt_convert": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "rrt_mlp_encode": (c_int, [c_void_p, c_int64, c_void_p, c_void_p]),
+    "rrt_mlp_workspace": (c_int, [c_int64, P(c_size_t)]),
+    "rrt_mlp_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                c_size_t, c_void_p]),
+    "rrt_mlp_backward": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_size_t, c_void_p]),
+    "rrt_mse": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "rrt_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              c_int, c_void_p]),
 }
 
 

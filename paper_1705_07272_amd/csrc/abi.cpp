@@ -80,6 +80,8 @@ static int validate_relight(const rrt_light* L, const rrt_rotations* R, const rr
     return fail(RRT_ERR_UNSUPPORTED, "relight: transport dtype %d (F32, BF16, E4M3 or S16)", T->dtype);
   if ((T->dtype == RRT_E4M3 || T->dtype == RRT_S16) && !T->block_scale && T->nvert > 0)
     return fail(RRT_ERR_INVALID, "relight: block-scaled transport needs block_scale");
+  if (T->cluster && (T->nclusters < 1 || !T->idx) && T->nvert > 0)
+    return fail(RRT_ERR_INVALID, "relight: per-cluster supports need nclusters >= 1 and an idx table");
   if (int64_t(R->nframes) * T->nvert > (int64_t(1) << 40))
     return fail(RRT_ERR_INVALID, "relight: output too large");
   return RRT_OK;
@@ -225,6 +227,8 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
   a.t_idx = T->idx;
   a.t_val = T->val;
   a.t_scale = T->block_scale;
+  a.cluster = T->cluster;
+  a.nclusters = T->cluster ? T->nclusters : 0;
   a.t_dtype = T->dtype;
   a.nnz = T->nnz;
   a.nvert = T->nvert;
@@ -260,6 +264,66 @@ int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst, 
   if ((dtype == RRT_E4M3 || dtype == RRT_S16) && !block_scale)
     return fail(RRT_ERR_INVALID, "convert: block-scaled dtype needs block_scale");
   return launch_convert(src, rows, cols, dtype, dst, block_scale, static_cast<hipStream_t>(stream));
+}
+
+int rrt_mlp_encode(const float* pos_nrm, int64_t B, void* x, void* stream) {
+  if (B < 0 || B > (int64_t(1) << 31) / RRT_MLP_IN) return fail(RRT_ERR_INVALID, "mlp_encode: B=%lld out of range", (long long)B);
+  if (B == 0) return RRT_OK;
+  if (!pos_nrm || !x) return fail(RRT_ERR_INVALID, "mlp_encode: null pointer");
+  return launch_mlp_encode(pos_nrm, B, x, static_cast<hipStream_t>(stream));
+}
+
+int rrt_mlp_workspace(int64_t B, size_t* bytes) {
+  if (!bytes) return fail(RRT_ERR_INVALID, "mlp_workspace: null bytes");
+  if (B < 0 || B > (int64_t(1) << 31) / RRT_MLP_HIDDEN) return fail(RRT_ERR_INVALID, "mlp_workspace: B=%lld out of range", (long long)B);
+  *bytes = mlp_workspace_bytes(B);
+  return RRT_OK;
+}
+
+static int check_mlp_batch(int64_t B, const char* what) {
+  if (B < 0 || B > (int64_t(1) << 31) / RRT_MLP_HIDDEN) return fail(RRT_ERR_INVALID, "%s: B=%lld out of range", what, (long long)B);
+  return RRT_OK;
+}
+
+int rrt_mlp_forward(const void* w, const float* bias, const void* x, int64_t B, float* out,
+                    void* ws, size_t ws_bytes, void* stream) {
+  int st = check_mlp_batch(B, "mlp_forward");
+  if (st) return st;
+  if (B == 0) return RRT_OK;
+  if (!w || !bias || !x || !out) return fail(RRT_ERR_INVALID, "mlp_forward: null pointer");
+  if ((st = check_ws(ws, ws_bytes, mlp_workspace_bytes(B), "mlp_forward"))) return st;
+  return launch_mlp_forward(w, bias, x, B, out, ws, static_cast<hipStream_t>(stream));
+}
+
+int rrt_mlp_backward(const void* w, const void* x, int64_t B, const float* dout, float* dw,
+                     float* db, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_mlp_batch(B, "mlp_backward");
+  if (st) return st;
+  if (B < 1) return fail(RRT_ERR_INVALID, "mlp_backward: empty batch");
+  if (!w || !x || !dout || !dw || !db) return fail(RRT_ERR_INVALID, "mlp_backward: null pointer");
+  if ((st = check_ws(ws, ws_bytes, mlp_workspace_bytes(B), "mlp_backward"))) return st;
+  return launch_mlp_backward(w, x, B, dout, dw, db, ws, static_cast<hipStream_t>(stream));
+}
+
+int rrt_mse(const float* out, const float* target, int64_t count, float* dout, double* loss,
+            void* stream) {
+  if (count < 0 || count > (int64_t(1) << 40)) return fail(RRT_ERR_INVALID, "mse: bad count");
+  if (count == 0) return RRT_OK;
+  if (!out || !target || !dout || !loss) return fail(RRT_ERR_INVALID, "mse: null pointer");
+  return launch_mse(out, target, count, dout, loss, static_cast<hipStream_t>(stream));
+}
+
+int rrt_adam_step(float* param, void* param_bf16, float* m, float* v, const float* grad,
+                  int64_t n, float lr, float beta1, float beta2, float eps, int step,
+                  void* stream) {
+  if (n < 0 || n > (int64_t(1) << 40)) return fail(RRT_ERR_INVALID, "adam: bad n");
+  if (step < 1) return fail(RRT_ERR_INVALID, "adam: step=%d < 1", step);
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+    return fail(RRT_ERR_INVALID, "adam: bad hyper-parameters");
+  if (n == 0) return RRT_OK;
+  if (!param || !m || !v || !grad) return fail(RRT_ERR_INVALID, "adam: null pointer");
+  return launch_adam(param, param_bf16, m, v, grad, n, lr, beta1, beta2, eps, step,
+                     static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -48,7 +48,9 @@ struct RelightLaunch {
   const float* frame_rot;   // [F][9] or nullptr
   const int32_t* t_idx;     // [V][nnz] or nullptr (dense)
   const void* t_val;        // [V][nnz]
-  const float* t_scale;     // [V][nblk] (E4M3) or nullptr
+  const float* t_scale;     // [V][nblk] (E4M3 / S16) or nullptr
+  const int32_t* cluster;   // [V] or nullptr (then t_idx is [C][nnz])
+  int nclusters;
   int t_dtype;
   int nnz;
   int64_t nvert;
@@ -58,6 +60,18 @@ struct RelightLaunch {
   float* out;               // [F][V]
 };
 int launch_relight(const RelightLaunch& a, hipStream_t s);
+
+// Learned decoder (mlp.hip).
+size_t mlp_workspace_bytes(int64_t B);
+int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s);
+int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, float* out,
+                       void* ws, hipStream_t s);
+int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* dout, float* dw,
+                        float* db, void* ws, hipStream_t s);
+int launch_mse(const float* out, const float* tgt, int64_t count, float* dout, double* loss,
+               hipStream_t s);
+int launch_adam(float* p, void* p_bf16, float* m, float* v, const float* g, int64_t n, float lr,
+                float b1, float b2, float eps, int step, hipStream_t s);
 
 // Storage conversion (convert.hip).
 int launch_convert(const float* src, int64_t rows, int cols, int dtype, void* dst,

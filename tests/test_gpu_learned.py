@@ -1,0 +1,134 @@
+"""The learned transport decoder on the device, end to end on a reduced
+displaced-sphere scene (6 x 64^2 faces, 12,000 vertices, 16 clusters).
+
+* per-cluster supports through the relight ABI give exactly the result of the
+  same rows passed per vertex;
+* the cluster-support relight matches the FP64 checker on the same stored
+  values (1e-5);
+* device training (forward, backward, Adam kernels) lowers the loss by an
+  order of magnitude, and the trained decoder's relit radiance on held-out
+  vertices is measured against the FP64 checker fed with per-vertex stored
+  rows it builds itself; the fallback rule then picks the form;
+* what the network gains: the device bytes of the decoder versus the stored
+  rows it replaces.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+N_FACE, V, K_CLUSTERS, NNZ = 64, 12000, 16, 256
+
+
+@pytest.fixture(scope="module")
+def scene():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_07272_amd as rrt
+    from paper_1705_07272_amd import learned
+    from oracle.relight import lighting_coefficients
+    from scenes.mesh import (displaced_sphere, learned_transport_pixels_torch, mesh_inputs,
+                             tangent_frames)
+    from scenes.scene import lighting_pixels
+    p, n, u, rho = displaced_sphere(4, V)
+    frames = tangent_frames(n)
+    feats = mesh_inputs(p, n)
+    _, labels = learned.kmeans(feats, K_CLUSTERS, iters=15, seed=1)
+
+    def pixels(ids):
+        ids = np.asarray(ids)
+        return learned_transport_pixels_torch(N_FACE, p[ids], frames[ids], u[ids], rho[ids],
+                                              "cuda", dtype=torch.float32)
+
+    li, lv = lighting_coefficients(lighting_pixels(4, N_FACE), 2048)
+    return dict(rrt=rrt, learned=learned, p=p, n=n, u=u, rho=rho, frames=frames, feats=feats,
+                labels=labels, pixels=pixels, li=li, lv=lv)
+
+
+def test_kmeans_labels_cover(scene):
+    counts = np.bincount(scene["labels"], minlength=K_CLUSTERS)
+    assert counts.min() > 0 and counts.sum() == V
+
+
+def test_cluster_rows_equal_per_vertex_rows(scene):
+    rrt = scene["rrt"]
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(V, 300, replace=False))
+    idx, val = rrt.project_rows(scene["pixels"](ids).contiguous(), NNZ)
+    rot = torch.from_numpy(scene["frames"][ids].astype(np.float32)).cuda()
+    li = torch.from_numpy(scene["li"]).cuda()
+    lv = torch.from_numpy(scene["lv"]).cuda()
+    a = rrt.relight(N_FACE, li, lv, rot, idx, val)
+    # the same rows as a per-"cluster" table, cluster[v] = v, reversed storage order
+    table = torch.flip(idx, [0]).contiguous()
+    cl = torch.arange(len(ids) - 1, -1, -1, dtype=torch.int32, device="cuda")
+    b = rrt.relight(N_FACE, li, lv, rot, table, val, cluster=cl)
+    assert torch.equal(a, b)
+
+
+def test_cluster_support_relight_parity(scene):
+    """Shared supports (rows of a [C, nnz] table) against the checker on the
+    same stored values."""
+    from cases import frame_errors
+    from oracle.relight import relight
+    rrt = scene["rrt"]
+    rng = np.random.default_rng(1)
+    ids = np.sort(rng.choice(V, 24, replace=False))
+    table = np.stack([np.sort(rng.choice(6 * N_FACE * N_FACE, NNZ, replace=False))
+                      for _ in range(K_CLUSTERS)]).astype(np.int32)
+    lab = scene["labels"][ids].astype(np.int32)
+    vals = rng.normal(size=(len(ids), NNZ)).astype(np.float32) * 1e-2
+    rot = scene["frames"][ids].astype(np.float32)
+    got = rrt.relight(N_FACE, torch.from_numpy(scene["li"]).cuda(),
+                      torch.from_numpy(scene["lv"]).cuda(), torch.from_numpy(rot).cuda(),
+                      torch.from_numpy(table).cuda(), torch.from_numpy(vals).cuda(),
+                      cluster=torch.from_numpy(lab).cuda()).cpu().numpy()
+    ref = relight(scene["li"], scene["lv"], N_FACE, rot, None, table[lab], vals)
+    assert max(frame_errors(got, ref)) <= 1e-5
+
+
+def test_train_decode_and_fallback(scene):
+    from cases import frame_errors
+    from oracle.relight import relight, transport_rows
+    from scenes.mesh import learned_transport_pixels
+    rrt, learned = scene["rrt"], scene["learned"]
+    labels = scene["labels"]
+    rng = np.random.default_rng(2)
+    perm = rng.permutation(V)
+    held, train = np.sort(perm[:1200]), np.sort(perm[1200:])
+    supports, scales = learned.cluster_supports(scene["pixels"], labels, K_CLUSTERS, NNZ,
+                                                sample_per_cluster=128)
+    targets = learned.targets_on_supports(scene["pixels"], train, labels, supports)
+    dec = learned.TransportDecoder(supports, scales, seed=3)
+    feats = torch.from_numpy(scene["feats"])
+    lab_t = torch.from_numpy(labels.astype(np.int32))
+    hist = dec.train(feats[train], targets, lab_t[train], steps=1500, batch=2048, lr=2e-3,
+                     log_every=100)
+    first, last = hist[0][1], hist[-1][1]
+    print(f"decoder loss {first:.4e} -> {last:.4e}")
+    assert last < 0.1 * first
+
+    # relit radiance of held-out vertices: decoder vs the checker on per-vertex rows
+    vals = dec.decode(feats[held], lab_t[held])
+    rot = torch.from_numpy(scene["frames"][held].astype(np.float32)).cuda()
+    li = torch.from_numpy(scene["li"]).cuda()
+    lv = torch.from_numpy(scene["lv"]).cuda()
+    mlp_rad = rrt.relight(N_FACE, li, lv, rot, dec.supports, vals,
+                          cluster=lab_t[held].cuda()).cpu().numpy()
+    sample = np.arange(0, len(held), len(held) // 16)
+    hs = held[sample]
+    T = learned_transport_pixels(N_FACE, scene["p"][hs], scene["frames"][hs], scene["u"][hs],
+                                 scene["rho"][hs])
+    ti, tv = transport_rows(T, NNZ)
+    ref = relight(scene["li"], scene["lv"], N_FACE, scene["frames"][hs].astype(np.float32), None,
+                  ti, tv)
+    err = max(frame_errors(mlp_rad[:, sample], ref))
+    form = learned.choose_form(err)
+    print(f"decoder held-out relit rel-L2 {err:.3e} -> form {form}")
+    assert form == ("mlp" if err <= 1e-3 else "stored")
+    assert err < 0.5                                   # a trained decoder, not noise
+    # what the decoder gains: bytes replacing V rows of (int32 index + bf16 value)
+    stored = V * NNZ * (4 + 2)
+    print(f"decoder {dec.parameter_bytes()} B vs stored rows {stored} B")
+    assert dec.parameter_bytes() * 20 < stored

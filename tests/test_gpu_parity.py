@@ -201,6 +201,52 @@ def test_relight_sparse(rrt, n, k, nnz, V):
     check_frames(run_relight(rrt, case), reference(case, return_scale=True), rel_l2=n >= 32)
 
 
+@pytest.mark.parametrize("n", [32, 64, 128])
+def test_relight_gather_exact(rrt, n):
+    """Source-index exactness inside relight (both gather paths): the
+    lighting is a texel-ID map (P[q] = q) and vertex row r holds a single
+    finest-level H, V or D coefficient, so each radiance is (+-a +-b +-c +-d)/2
+    of four gathered source indices.  A wrong index moves a result by at
+    least 1/2; reconstruction rounding stays below 0.05.  Random,
+    boundary-heavy (22.5 / 45 degree) and cube-group rotations."""
+    from oracle.haar import haar_forward
+    from oracle.sphere import quantise_rotation, rotate_pixels
+    from scenes.scene import random_rotations
+    ids = np.arange(6 * n * n, dtype=np.float64).reshape(6, n, n)
+    light = haar_forward(ids).ravel().astype(np.float32)
+    light_idx = np.arange(6 * n * n, dtype=np.int32)
+    h = n // 2
+    rr, cc = np.meshgrid(np.arange(h), np.arange(h), indexing="ij")
+    pos = []
+    for f in range(6):
+        for (dr, dc) in [(0, h), (h, 0), (h, h)]:        # H, V, D quadrants of level 1
+            pos.append(f * n * n + (rr + dr) * n + (cc + dc))
+    rows = np.concatenate([p_.ravel() for p_ in pos]).astype(np.int32)
+    V = rows.size
+    rots = list(random_rotations(500 + n, 3))
+    for ang in (np.pi / 4, np.pi / 8):
+        c_, s_ = np.cos(ang), np.sin(ang)
+        rots.append(np.array([[c_, -s_, 0], [s_, c_, 0], [0, 0, 1]]))
+    rots.append(np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]]))
+    for R in rots:
+        R = np.asarray(R, np.float32)
+        out = rrt.relight(n, dev(light_idx), dev(light), dev(np.tile(R, (V, 1, 1))),
+                          dev(rows.reshape(V, 1)), dev(np.ones((V, 1), np.float32)))
+        got = out.cpu().numpy()[0]
+        want = haar_forward(rotate_pixels(ids, quantise_rotation(R))).ravel()[rows]
+        err = np.abs(got - want)
+        assert err.max() < 0.05, (R, int((err >= 0.05).sum()), float(err.max()))
+
+
+@pytest.mark.parametrize("n,V", [(512, 3), (1024, 2)])
+def test_relight_large_faces(rrt, n, V):
+    """n = 512 and 1024: many regions per face and the FP64 levels above them."""
+    from cases import build_case, reference, workload
+    w = workload(310 + n, n, 4096, V, 256, exp_lo=1.0, exp_hi=4.0)
+    case = build_case(w)
+    check_frames(run_relight(rrt, case), reference(case, return_scale=True))
+
+
 def test_relight_frames_composition(rrt):
     """Frame rotations composed with vertex frames (fixed-point rule)."""
     from cases import build_case, reference, workload
