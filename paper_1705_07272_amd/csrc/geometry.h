@@ -101,14 +101,12 @@ __device__ __forceinline__ int exact_floor(int s, int D, int logh, int q0) {
 // column j = min(n-1, floor(h (sc + D) / D)), h = n / 2, D = |d_a|; row i
 // likewise from tc.
 //
-// h (sc + D) / D = h sc / D + h (in [0, 2h]) is estimated in binary32 as
-// fma(float(sc), h rcp(D), h): float(sc) rounds once (2^-24), v_rcp_f32 is
-// within one ulp (2^-23), the fma rounds once (at most 2h 2^-24), so the
-// estimate is within h 2^-21 of the exact value.  When its fractional part
-// is at least eps = h 2^-19 away from an integer the floor is exact;
-// otherwise (rare) the int64 test decides.  Every output is in [0, 6 n^2)
-// for any proper rotation; malformed input only yields some other index.
-__device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
+// Exact form: integer face selection, a binary32 estimate of h sc / D + h
+// (float(sc) and float(D) round once each (2^-24), v_rcp_f32 is within one
+// ulp (2^-23), the fma rounds once (at most 2h 2^-24): within h 2^-21 of the
+// exact value, so its floor is off by at most one) and an int64 test on each
+// side of the estimate.  Every output is in [0, 6 n^2).
+__device__ __forceinline__ int source_texel_exact(int x, int y, int z, int logn) {
   const int n = 1 << logn;
   const int logh = logn - 1;
   const int h = 1 << logh;
@@ -126,18 +124,41 @@ __device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float
   const int tc = py ? (neg ? nz : z) : ny;
   const float hf = float(h);
   const float hr = hf * __builtin_amdgcn_rcpf(float(D));
-  const float qs = __builtin_fmaf(float(sc), hr, hf);
-  const float qt = __builtin_fmaf(float(tc), hr, hf);
-  const float fs = floorf(qs), ft = floorf(qt);
-  int j = int(fs), i = int(ft);
-  const float es = qs - fs, et = qt - ft;
-  if (fminf(fminf(es, 1.0f - es), fminf(et, 1.0f - et)) < eps) {
-    j = h + exact_floor(sc, D, logh, j - h);
-    i = h + exact_floor(tc, D, logh, i - h);
-  }
-  j = min(j, n - 1);
-  i = min(i, n - 1);
+  const int j0 = int(floorf(__builtin_fmaf(float(sc), hr, hf)));
+  const int i0 = int(floorf(__builtin_fmaf(float(tc), hr, hf)));
+  const int j = min(h + exact_floor(sc, D, logh, j0 - h), n - 1);
+  const int i = min(h + exact_floor(tc, D, logh, i0 - h), n - 1);
   return (face << (2 * logn)) + (i << logn) + j;
+}
+
+// The same map, with a binary32 fast path on the cube-map instructions
+// (v_cubeid / v_cubesc / v_cubetc / v_cubema: face, in-face coordinates and
+// twice the major component, in the face convention above, ties resolved
+// towards z then y).
+//
+// The components are converted to binary32 (relative error 2^-24 each) and
+// q = h sc / D + h + eps is estimated as fma(sc, n rcp(|ma|), h + eps); as
+// for the exact form its error is below h 2^-21 < eps.  If frac(q) >= 2 eps
+// for both coordinates, the exact quotient lies strictly between the same
+// two integers as q - eps, so trunc(q) is the exact floor (and lies in
+// [0, n - 1]); otherwise the exact form decides.
+//
+// A face chosen by the binary32 comparison that differs from the exact one
+// (a near tie |d_a| ~ |d_b| or an exact tie broken the other way) is always
+// caught: the exact major component then appears as an in-face coordinate
+// with |a_f| / |b_f| in [1 - 2^-23, 1], so that coordinate's q is within
+// h 2^-21 + eps of 0 or 2h and fails the margin test.  A zero direction gives
+// NaN and also takes the exact form.  Every output is in [0, 6 n^2).
+__device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
+  const float fx = float(x), fy = float(y), fz = float(z);
+  const float hr = float(1 << logn) * __builtin_amdgcn_rcpf(fabsf(__builtin_amdgcn_cubema(fx, fy, fz)));
+  const float off = float(1 << (logn - 1)) + eps;
+  const float qs = __builtin_fmaf(__builtin_amdgcn_cubesc(fx, fy, fz), hr, off);
+  const float qt = __builtin_fmaf(__builtin_amdgcn_cubetc(fx, fy, fz), hr, off);
+  const float es = __builtin_amdgcn_fractf(qs), et = __builtin_amdgcn_fractf(qt);
+  if (!(fminf(es, et) >= 2.0f * eps)) return source_texel_exact(x, y, z, logn);
+  const int face = int(__builtin_amdgcn_cubeid(fx, fy, fz));
+  return (face << (2 * logn)) + (int(qt) << logn) + int(qs);
 }
 
 // Margin of the binary32 quotient estimate (see source_texel).

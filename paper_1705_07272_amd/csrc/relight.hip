@@ -172,18 +172,6 @@ struct RelightParams {
   int comp;
 };
 
-// Source face of d when |d_a| strictly exceeds the other two components
-// (so no tie rule is involved), else -1.  The set of such directions for one
-// face is an open convex cone: if the four corner texel centres of a tile
-// are in it, every texel centre of the tile is.
-__device__ __forceinline__ int strict_face(int3 d) {
-  const int ax = max(d.x, -d.x), ay = max(d.y, -d.y), az = max(d.z, -d.z);
-  if (ax > ay && ax > az) return d.x > 0 ? 0 : 1;
-  if (ay > ax && ay > az) return d.y > 0 ? 2 : 3;
-  if (az > ax && az > ay) return d.z > 0 ? 4 : 5;
-  return -1;
-}
-
 // 2x2 levels with block side 2..T inside a thread's T x T tile, in place
 // (S stays at the block corner, H/V/D at the corner + B/2 offsets).
 template <int T>
@@ -224,66 +212,6 @@ __device__ __forceinline__ void gather_general(float (&g)[T][T], int3 d0, const 
   }
 }
 
-// Component `comp` of v times `sign`.
-__device__ __forceinline__ int signed_component(int3 v, int comp, int sign) {
-  return sign * (comp == 0 ? v.x : (comp == 1 ? v.y : v.z));
-}
-
-// Gather of a tile whose texel centres all lie strictly inside the pyramid of
-// source face `sface`: the major axis and the in-face coordinate signs are
-// fixed, so D, sc and tc are affine in the texel position and advance by
-// constant integer steps; only the two floor quotients remain per texel.
-template <int T, typename SrcT>
-__device__ __forceinline__ void gather_uniform(float (&g)[T][T], int3 d0, const FaceAxes& ax,
-                                               int sface, __amdgpu_buffer_rsrc_t src, int logn,
-                                               float eps) {
-  const int n = 1 << logn;
-  const int logh = logn - 1;
-  const float hf = float(1 << logh);
-  const int axis = sface >> 1;
-  const int sgn = (sface & 1) ? -1 : 1;
-  // in-face coordinates per face: +X(-z,-y) -X(z,-y) +Y(x,z) -Y(x,-z) +Z(x,-y) -Z(-x,-y)
-  const int s_comp = axis == 0 ? 2 : 0;
-  const int s_sgn = (sface == 0 || sface == 5) ? -1 : 1;
-  const int t_comp = axis == 1 ? 2 : 1;
-  const int t_sgn = sface == 2 ? 1 : -1;
-  const int3 su = make_int3(2 * ax.mU.x, 2 * ax.mU.y, 2 * ax.mU.z);
-  const int3 sv = make_int3(2 * ax.mV.x, 2 * ax.mV.y, 2 * ax.mV.z);
-  int D_r = signed_component(d0, axis, sgn), sc_r = signed_component(d0, s_comp, s_sgn),
-      tc_r = signed_component(d0, t_comp, t_sgn);
-  const int dD_c = signed_component(su, axis, sgn), dsc_c = signed_component(su, s_comp, s_sgn),
-            dtc_c = signed_component(su, t_comp, t_sgn);
-  const int dD_r = signed_component(sv, axis, sgn), dsc_r = signed_component(sv, s_comp, s_sgn),
-            dtc_r = signed_component(sv, t_comp, t_sgn);
-  const int face_off = sface << (2 * logn);
-#pragma unroll
-  for (int r = 0; r < T; ++r) {
-    int D = D_r, sc = sc_r, tc = tc_r;
-#pragma unroll
-    for (int c = 0; c < T; ++c) {
-      const float hr = hf * __builtin_amdgcn_rcpf(float(D));
-      const float qs = __builtin_fmaf(float(sc), hr, hf);
-      const float qt = __builtin_fmaf(float(tc), hr, hf);
-      const float fs = floorf(qs), ft = floorf(qt);
-      int j = int(fs), i = int(ft);
-      const float es = qs - fs, et = qt - ft;
-      if (fminf(fminf(es, 1.0f - es), fminf(et, 1.0f - et)) < eps) {
-        j = (1 << logh) + exact_floor(sc, D, logh, j - (1 << logh));
-        i = (1 << logh) + exact_floor(tc, D, logh, i - (1 << logh));
-      }
-      j = min(j, n - 1);
-      i = min(i, n - 1);
-      g[r][c] = load_src<SrcT>(src, face_off + (i << logn) + j);
-      D += dD_c;
-      sc += dsc_c;
-      tc += dtc_c;
-    }
-    D_r += dD_r;
-    sc_r += dsc_r;
-    tc_r += dtc_r;
-  }
-}
-
 // Q: region side (power of two, <= 128); tiles of T x T texels per thread.
 template <int Q, typename SrcT>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
@@ -298,9 +226,6 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   __shared__ double gS[GMAX * GMAX];
   __shared__ float red_s[kThreads / 64], red_c[kThreads / 64];
   __shared__ unsigned face_mask;
-  __shared__ uint8_t tile_list[TS * TS];
-  __shared__ int8_t tile_face[TS * TS];
-  __shared__ int wave_count[kThreads / 64];
 
   const int tid = threadIdx.x;
   const int64_t v = blockIdx.x;
@@ -350,58 +275,8 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
 
       for (int reg = 0; reg < G * G; ++reg) {
         const int gy = reg / G, gx = reg - gy * G;
-        // Tiles whose texel centres all fall strictly inside one source face
-        // take the cheaper gather; they are packed first so that only the
-        // wave straddling the split runs both gathers.
-        int my_tile = tid, my_face = -1;
-        if (T >= 2) {
-          int sface = -1;
-          if (owns_tile) {
-            const int ty = tid >> LOGTS, tx = tid & (TS - 1);
-            const int i0 = (gy << LOGQ) + ty * T, j0 = (gx << LOGQ) + tx * T;
-            const int U0 = 2 * j0 + 1 - n, V0 = 2 * i0 + 1 - n;
-            int3 d;
-            d.x = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
-            d.y = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
-            d.z = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
-            sface = strict_face(d);
-            const int3 e1 = make_int3(wrap_mad(ax.mU.x, 2 * (T - 1), d.x),
-                                      wrap_mad(ax.mU.y, 2 * (T - 1), d.y),
-                                      wrap_mad(ax.mU.z, 2 * (T - 1), d.z));
-            const int3 e2 = make_int3(wrap_mad(ax.mV.x, 2 * (T - 1), d.x),
-                                      wrap_mad(ax.mV.y, 2 * (T - 1), d.y),
-                                      wrap_mad(ax.mV.z, 2 * (T - 1), d.z));
-            const int3 e3 = make_int3(wrap_mad(ax.mV.x, 2 * (T - 1), e1.x),
-                                      wrap_mad(ax.mV.y, 2 * (T - 1), e1.y),
-                                      wrap_mad(ax.mV.z, 2 * (T - 1), e1.z));
-            if (strict_face(e1) != sface || strict_face(e2) != sface || strict_face(e3) != sface)
-              sface = -1;
-          }
-          const bool uni = sface >= 0;
-          const uint64_t ballot = __ballot(uni);
-          const int lane = tid & 63, wave = tid >> 6;
-          const int before = __popcll(ballot & ((uint64_t(1) << lane) - 1));
-          if (lane == 0) wave_count[wave] = __popcll(ballot);
-          __syncthreads();
-          int base = 0, n_uni = 0;
-#pragma unroll
-          for (int w = 0; w < kThreads / 64; ++w) {
-            base += (w < wave) ? wave_count[w] : 0;
-            n_uni += wave_count[w];
-          }
-          if (owns_tile) {
-            const int slot = uni ? base + before : n_uni + (tid - base - before);
-            tile_list[slot] = uint8_t(tid);
-            tile_face[slot] = int8_t(sface);
-          }
-          __syncthreads();
-          if (owns_tile) {
-            my_tile = tile_list[tid];
-            my_face = tile_face[tid];
-          }
-        }
         if (owns_tile) {
-          const int ty = my_tile >> LOGTS, tx = my_tile & (TS - 1);
+          const int ty = tid >> LOGTS, tx = tid & (TS - 1);
           float g[T][T];
           const int i0 = (gy << LOGQ) + ty * T, j0 = (gx << LOGQ) + tx * T;
           const int U0 = 2 * j0 + 1 - n, V0 = 2 * i0 + 1 - n;
@@ -409,11 +284,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
           d0.x = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
           d0.y = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
           d0.z = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
-          if (my_face >= 0) {
-            gather_uniform<T, SrcT>(g, d0, ax, my_face, src, logn, eps);
-          } else {
-            gather_general<T, SrcT>(g, d0, ax, src, logn, eps);
-          }
+          gather_general<T, SrcT>(g, d0, ax, src, logn, eps);
           tile_levels<T>(g);
 #pragma unroll
           for (int r = 0; r < T; ++r)
@@ -543,7 +414,10 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   const int dx = wrap_mad(ax.mU.x, U, wrap_mad(ax.mV.x, V, wrap_mad(ax.mN.x, n, 0)));
   const int dy = wrap_mad(ax.mU.y, U, wrap_mad(ax.mV.y, V, wrap_mad(ax.mN.y, n, 0)));
   const int dz = wrap_mad(ax.mU.z, U, wrap_mad(ax.mV.z, V, wrap_mad(ax.mN.z, n, 0)));
-  dst[int64_t(r) * 6 * per_face + q] = src[source_texel(dx, dy, dz, logn, quotient_margin(logn))];
+  // the map stays in [0, 6 n^2) by construction; the clamp keeps this plain
+  // pointer read in bounds whatever the rotation holds
+  const unsigned at = unsigned(source_texel(dx, dy, dz, logn, quotient_margin(logn)));
+  dst[int64_t(r) * 6 * per_face + q] = src[min(at, unsigned(6 * per_face - 1))];
 }
 
 template <int Q, typename SrcT>
