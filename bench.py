@@ -128,6 +128,114 @@ def device_inputs(w, form, batch=2048):
     return dict(pix=pix, rot=rot, frot=frot, idx=idx, val=val, scale=scale)
 
 
+def run_learned(args, w):
+    """Learned-decoder form on the displaced-sphere workload: setup (k-means,
+    supports, targets, device training, held-out error against the stored
+    per-vertex rows) untimed; the timed step is a1-a3 + decode + relight."""
+    import numpy as np
+    import torch
+
+    import paper_1705_07272_amd as rrt
+    from paper_1705_07272_amd import learned
+    from scenes.mesh import (displaced_sphere, learned_transport_pixels_torch, mesh_inputs,
+                             tangent_frames)
+    from scenes.scene import lighting_pixels
+    t0 = time.perf_counter()
+    p, nrm, u, rho = displaced_sphere(w.cfg, w.nverts)
+    frames = tangent_frames(nrm)
+    feats = mesh_inputs(p, nrm)
+    _, labels = learned.kmeans(feats, 64, iters=25, seed=1)
+
+    def pixels(ids):
+        ids = np.asarray(ids)
+        return learned_transport_pixels_torch(w.n, p[ids], frames[ids], u[ids], rho[ids], "cuda",
+                                              dtype=torch.float32)
+
+    supports, scales = learned.cluster_supports(pixels, labels, 64, w.nnz, sample_per_cluster=256)
+    perm = np.random.default_rng(7).permutation(w.nverts)
+    held, train = np.sort(perm[: w.nverts // 10]), np.sort(perm[w.nverts // 10:])
+    targets = learned.targets_on_supports(pixels, train, labels, supports)
+    dec = learned.TransportDecoder(supports, scales, seed=3)
+    f_all = torch.from_numpy(feats)
+    lab_all = torch.from_numpy(labels.astype(np.int32))
+    hist = dec.train(f_all[train], targets, lab_all[train], steps=args.mlp_steps, batch=4096,
+                     lr=2e-3, log_every=max(1, args.mlp_steps // 10))
+    del targets
+    print(f"learned setup {time.perf_counter() - t0:.1f} s, loss {hist[0][1]:.3e} -> "
+          f"{hist[-1][1]:.3e}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda")
+    pix = torch.from_numpy(lighting_pixels(w.cfg, w.n)).to(dev)
+    rot = torch.from_numpy(frames.astype(np.float32)).to(dev)
+    feats_dev = f_all.to(dev)
+    lab_dev = lab_all.to(dev)
+    ws = torch.empty(2 * 6 * w.n * w.n * 4 + 512, dtype=torch.uint8, device=dev)
+    out = torch.empty((1, w.nverts), dtype=torch.float32, device=dev)
+
+    # held-out error of the decoder against the stored per-vertex rows
+    coef = rrt.haar_forward(pix)
+    li, lv = rrt.topk(coef.view(1, -1), w.k_light)
+    prep = rrt.prepare_lighting(w.n, li[0], lv[0], workspace=ws)
+    hold = torch.from_numpy(held).to(dev).long()
+    vals = dec.decode(f_all[held], lab_all[held])
+    r_mlp = rrt.relight_prepared(prep, rot[hold].contiguous(), dec.supports, vals,
+                                 cluster=lab_dev[hold].contiguous())
+    rows_i, rows_v = [], []
+    for s in range(0, len(held), 512):
+        i, v = rrt.project_rows(pixels(held[s:s + 512]).contiguous(), w.nnz)
+        rows_i.append(i)
+        rows_v.append(v)
+    r_rows = rrt.relight_prepared(prep, rot[hold].contiguous(), torch.cat(rows_i), torch.cat(rows_v))
+    err = float(torch.linalg.norm((r_mlp - r_rows).double()) / torch.linalg.norm(r_rows.double()))
+    form = learned.choose_form(err)
+
+    def step(ev=None):
+        coef = rrt.haar_forward(pix)
+        li, lv = rrt.topk(coef.view(1, -1), w.k_light)
+        prep = rrt.prepare_lighting(w.n, li[0], lv[0], workspace=ws)
+        if ev is not None:
+            ev[0].record()
+        vals = dec.decode(feats_dev, lab_dev)
+        if ev is not None:
+            ev[1].record()
+        rrt.relight_prepared(prep, rot, dec.supports, vals, cluster=lab_dev, out=out)
+        if ev is not None:
+            ev[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for k in range(args.steps):
+        step(evs[k])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    ms_dec = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    ms_rel = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    flops = 2.0 * w.nverts * sum(o * i for (o, i) in learned.LAYER_SHAPES)
+    print(json.dumps({
+        "metric": "relit vertices/s at rel-L2<=1e-3 vs FP64 oracle: plain FP32 vs BF16+MLP",
+        "value": round(w.nverts / (ms * 1e-3), 1), "unit": "relit vertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 decoder weights/activations, f32 accumulate, f32 relight",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cube_face": w.n, "light_coeffs": w.k_light,
+                   "vertices": w.nverts, "clusters": 64, "form": "mlp",
+                   "train_steps": args.mlp_steps},
+        "learned": {"heldout_rel_l2_vs_stored_rows": err, "form_selected": form,
+                    "decoder_bytes": dec.parameter_bytes(),
+                    "stored_rows_bytes_bf16": w.nverts * w.nnz * 6,
+                    "decode_ms": round(ms_dec, 4), "relight_ms": round(ms_rel, 4),
+                    "decode_tflops": round(flops / (ms_dec * 1e-3) / 1e12, 2),
+                    "mfma_bf16_peak_tflops": 2500.0},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,10 +243,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2, help="scene configuration (2 = 6x128^2, "
                     "top-1024 lighting, 50,000 vertices, CSR-256 FP32, 1 frame)")
-    ap.add_argument("--form", choices=["f32", "bf16", "s16", "e4m3"], default="f32",
+    ap.add_argument("--form", choices=["f32", "bf16", "s16", "e4m3", "mlp"], default="f32",
                     help="transport storage; the reduced forms also store the lighting in "
                          "binary16 and accumulate with compensation")
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--mlp-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
@@ -153,7 +262,7 @@ def main():
     w = WORKLOADS[args.workload]
 
     base = None
-    if not args.no_cpu_baseline and not args.copy_calibration:
+    if not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp":
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
         base = cpu_baseline(args.workload, args.cpu_sample, workers)
         print(f"cpu baseline done: {base['sample']}", file=sys.stderr, flush=True)
@@ -170,6 +279,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}))
+        return
+
+    if args.form == "mlp":
+        run_learned(args, WORKLOADS[4] if args.workload == 2 else w)
         return
 
     inp = device_inputs(w, args.form)

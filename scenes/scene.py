@@ -73,6 +73,8 @@ WORKLOADS = {
                 1.0, 200.0, "random"),
     3: Workload(3, "cube128_k1024_csr256_v50000_f64", 128, 1024, 50000, 64, 256,
                 1.0, 200.0, "random"),
+    4: Workload(4, "cube256_k2048_mesh_v200000_mlp", 256, 2048, 200000, 1, 256,
+                1.0, 200.0, "mesh"),
     5: Workload(5, "cube256_k2048_csr256_v1000000_f64", 256, 2048, 1000000, 64, 256,
                 1.0, 500.0, "random"),
 }

@@ -146,3 +146,33 @@ def test_convert_validation(rrt):
     assert lib.rrt_convert(_p(8), 2, 3, E.RRT_S16, _p(8), None, None) == E.RRT_ERR_INVALID
     assert lib.rrt_convert(_p(0), 2, 3, E.RRT_BF16, _p(8), None, None) == E.RRT_ERR_INVALID
     assert lib.rrt_convert(_p(0), 0, 3, E.RRT_BF16, _p(0), None, None) == E.RRT_OK
+
+
+def test_cluster_transport_validation(rrt):
+    E = rrt._abi
+    L, R, T = _desc(rrt)
+    T.cluster = 8
+    T.nclusters = 0
+    assert _relight_ws(rrt, L, R, T)[0] == E.RRT_ERR_INVALID
+    T.nclusters = 4
+    assert _relight_ws(rrt, L, R, T)[0] == E.RRT_OK
+    T.idx = 0
+    assert _relight_ws(rrt, L, R, T)[0] == E.RRT_ERR_INVALID
+
+
+def test_mlp_validation(rrt):
+    lib = rrt.lib
+    E = rrt._abi
+    nb = ctypes.c_size_t(0)
+    assert lib.rrt_mlp_workspace(4096, ctypes.byref(nb)) == E.RRT_OK and nb.value > 4096 * 256 * 20
+    assert lib.rrt_mlp_workspace(-1, ctypes.byref(nb)) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_encode(_p(0), 10, _p(8), None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_encode(_p(0), 0, _p(0), None) == E.RRT_OK
+    assert lib.rrt_mlp_forward(_p(8), _p(8), _p(8), 64, _p(8), _p(256), 16, None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_mlp_forward(_p(0), _p(8), _p(8), 64, _p(8), _p(256), 1 << 30, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_backward(_p(8), _p(8), 0, _p(8), _p(8), _p(8), _p(256), 1 << 30, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mse(_p(0), _p(8), 10, _p(8), _p(8), None) == E.RRT_ERR_INVALID
+    f = ctypes.c_float
+    assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(0.9), f(0.999), f(1e-8), 0, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(1.0), f(0.999), f(1e-8), 1, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_adam_step(_p(0), None, _p(0), _p(0), _p(0), 0, f(1e-3), f(0.9), f(0.999), f(1e-8), 1, None) == E.RRT_OK

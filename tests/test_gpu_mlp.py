@@ -4,8 +4,9 @@
 Tolerances: the device keeps activations in bfloat16 between layers (each
 store rounds by up to 2^-9) and accumulates in FP32, so outputs and
 gradients are compared by relative L2 error: forward <= 2e-2, gradients
-<= 3e-2 per tensor; the encoding within 2 bfloat16 ulps; MSE and Adam (pure
-FP32 elementwise) within 1e-5 relative.
+<= 3e-2 per tensor; the encoding within 2 bfloat16 ulps plus 1e-4 (binary32
+argument rounding of the highest band); MSE and Adam (pure FP32
+elementwise) within 1e-5 relative.
 """
 import numpy as np
 import pytest
@@ -48,8 +49,10 @@ def test_encode(rrt):
     x = rng.uniform(-1, 1, size=(1000, 6)).astype(np.float32)
     got = rrt.mlp_encode(torch.from_numpy(x).cuda()).float().cpu().numpy()
     want = ref.encode(x.astype(np.float64))
+    # bfloat16 storage (half ulp 2^-8 relative) plus the binary32 rounding of
+    # the argument 2^7 pi x of the highest band (about 2^7 pi 2^-24 absolute)
     ulp = np.maximum(np.abs(want), 2.0 ** -126) * 2.0 ** -7
-    assert np.all(np.abs(got - want) <= 2 * ulp + 1e-6)
+    assert np.all(np.abs(got - want) <= 2 * ulp + 1e-4)
     assert np.all(got[:, 102:] == 0)
 
 
