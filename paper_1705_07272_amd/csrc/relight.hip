@@ -33,11 +33,18 @@ namespace rrt {
 namespace {
 
 constexpr int kThreads = 256;
-// Region side for large faces: a 64 x 64 region (16 KiB LDS image, 4 x 4
-// texels per thread) leaves room for five 256-thread workgroups per CU,
-// which hides the gather latency better than 128 x 128 regions (64 KiB,
-// two workgroups per CU); measured on MI355X at n = 128.
-constexpr int kMaxRegion = 64;
+constexpr int kWaves = kThreads / 64;
+// Block side of one wave's unit of work: a 32 x 32 block is 8 x 8 tiles of
+// 4 x 4 texels, one tile per lane, so every Haar level up to the block stays
+// inside the wave (registers, then lane shuffles) and needs no barrier.
+constexpr int kBlock = 32;
+// Transport entries of a vertex listed in LDS (bucketed by consuming wave);
+// entries past this count are decoded from global memory in every block.
+constexpr int kMaxListed = 2048;
+constexpr int kMaxChunks = kMaxListed / kThreads;
+// LDS for the FP64 block sums of the faces processed together.
+constexpr int kGroupBytes = 16384;
+constexpr int kOwners = kWaves + 1;  // one entry list per wave, one for coarse entries
 
 // Gathers from the source map go through a raw buffer resource: 32-bit
 // offsets (no 64-bit address arithmetic per texel) and hardware range
@@ -170,10 +177,16 @@ struct RelightParams {
   int logn;
   int dtype;
   int comp;
+  int listed;       // entries of each row listed in LDS: min(nnz, kMaxListed)
+  int group_faces;  // faces whose block sums fit in LDS together
 };
 
-// 2x2 levels with block side 2..T inside a thread's T x T tile, in place
-// (S stays at the block corner, H/V/D at the corner + B/2 offsets).
+// Unscaled 2x2 levels with block side 2..T inside a thread's T x T tile, in
+// place (S stays at the block corner, H/V/D at the corner + B/2 offsets):
+// S' = (a + b) + (c + d), H' = (a - b) + (c - d), V' = (a + b) - (c + d),
+// D' = (a - b) - (c - d).  A coefficient of a block of side B is then B
+// times the orthonormal one; the factor is a power of two and is removed
+// exactly where the coefficient is read.
 template <int T>
 __device__ __forceinline__ void tile_levels(float (&g)[T][T]) {
 #pragma unroll
@@ -184,58 +197,103 @@ __device__ __forceinline__ void tile_levels(float (&g)[T][T]) {
       for (int c0 = 0; c0 < T; c0 += B) {
         const int h = B / 2;
         const float a = g[r0][c0], b = g[r0][c0 + h], c = g[r0 + h][c0], d = g[r0 + h][c0 + h];
-        g[r0][c0] = 0.5f * ((a + b) + (c + d));
-        g[r0][c0 + h] = 0.5f * ((a - b) + (c - d));
-        g[r0 + h][c0] = 0.5f * ((a + b) - (c + d));
-        g[r0 + h][c0 + h] = 0.5f * ((a - b) - (c - d));
+        g[r0][c0] = (a + b) + (c + d);
+        g[r0][c0 + h] = (a - b) + (c - d);
+        g[r0 + h][c0] = (a + b) - (c + d);
+        g[r0 + h][c0 + h] = (a - b) - (c - d);
       }
   }
 }
 
-// General gather of a tile: the full source-texel map per texel.
-template <int T, typename SrcT>
-__device__ __forceinline__ void gather_general(float (&g)[T][T], int3 d0, const FaceAxes& ax,
-                                               __amdgpu_buffer_rsrc_t src, int logn, float eps) {
-#pragma unroll
-  for (int r = 0; r < T; ++r) {
-    int dx = d0.x, dy = d0.y, dz = d0.z;
-#pragma unroll
-    for (int c = 0; c < T; ++c) {
-      g[r][c] = load_src<SrcT>(src, source_texel(dx, dy, dz, logn, eps));
-      dx = wrap_mad(ax.mU.x, 2, dx);
-      dy = wrap_mad(ax.mU.y, 2, dy);
-      dz = wrap_mad(ax.mU.z, 2, dz);
-    }
-    d0.x = wrap_mad(ax.mV.x, 2, d0.x);
-    d0.y = wrap_mad(ax.mV.y, 2, d0.y);
-    d0.z = wrap_mad(ax.mV.z, 2, d0.z);
-  }
+// Row stride of a wave's Q x Q block image in LDS: padded by 8 floats for
+// Q >= 16 so that the 8 rows of an 8 x 8 patch, and the 8 tiles read by 8
+// lanes, fall in distinct banks.
+constexpr int image_stride(int Q) { return Q >= 16 ? Q + 8 : Q; }
+// Key of a block entry: log2 of its block side (3 bits), block number
+// (13 bits) and image offset (11 bits, < 32 * 40).
+constexpr int kOffBits = 11;
+constexpr int kBlockBits = 13;
+constexpr int kLogbShift = kOffBits + kBlockBits;
+
+// LDS ordering among the lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Q: region side (power of two, <= 128); tiles of T x T texels per thread.
+// Index of the k-th set bit of a face mask (k < popcount).
+__device__ __forceinline__ int nth_face(unsigned faces, int k) {
+  int face = 0;
+  for (int f = 0; f < 6; ++f) {
+    if ((faces >> f) & 1u) {
+      if (k == 0) face = f;
+      --k;
+    }
+  }
+  return face;
+}
+
+// Where a transport entry is consumed when the faces of rank [g0, g0 + FG)
+// among `faces` are processed together.  Block gi = (face rank - g0) G^2 +
+// block row * G + block column holds every coefficient of a block at most Q
+// wide except the face's scaling coefficient; those go to the wave
+// gi mod kWaves, keyed by their block side, gi and position in the block
+// image (the image holds unscaled coefficients).  The
+// others (blocks wider than Q, and the face's scaling coefficient) are
+// "coarse": owner kWaves, key = index of the group's in-place block-sum
+// grid.  Returns -1 for entries outside the group or invalid indices.
+template <int Q>
+__device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces, int g0, int FG,
+                                        int& key) {
+  constexpr int LOGQ = __builtin_ctz(Q);
+  constexpr int STRIDE = image_stride(Q);
+  const Slot s = decode_slot(idx, logn);
+  if (s.face < 0 || !((faces >> s.face) & 1u)) return -1;
+  const int rank = __popc(faces & ((1u << s.face) - 1u)) - g0;
+  if (rank < 0 || rank >= FG) return -1;
+  const int gi = rank * G * G + (s.pr >> LOGQ) * G + (s.pc >> LOGQ);
+  if (s.logb <= LOGQ && (s.pr | s.pc) != 0) {
+    key = (s.logb << kLogbShift) | (gi << kOffBits) | ((s.pr & (Q - 1)) * STRIDE + (s.pc & (Q - 1)));
+    return gi & (kWaves - 1);
+  }
+  key = gi;
+  return kWaves;
+}
+
+// Q: block side (min(n, kBlock)); a wave's TS x TS lanes each own a T x T tile.
 template <int Q, typename SrcT>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
-  constexpr int TS = Q >= 16 ? 16 : Q;  // tiles per region side
-  constexpr int T = Q / TS;             // texels per tile side
+  constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
+  constexpr int T = Q / TS;           // texels per tile side
   constexpr int LOGQ = __builtin_ctz(Q);
-  constexpr int LOGTS = __builtin_ctz(TS);
-  // regions per face side: one below the largest region side, else up to n = 1024
-  constexpr int GMAX = Q < kMaxRegion ? 1 : 1024 / Q;
-  __shared__ float img[Q * Q];
-  __shared__ double tS[TS * TS];
-  __shared__ double gS[GMAX * GMAX];
-  __shared__ float red_s[kThreads / 64], red_c[kThreads / 64];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __shared__ int cnt[kMaxChunks][kWaves][kOwners];
+  __shared__ int lbase[kOwners], lcount[kOwners];
+  __shared__ float red_s[kWaves], red_c[kWaves];
   __shared__ unsigned face_mask;
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar registers
   const int64_t v = blockIdx.x;
   const int logn = p.logn;
   const int n = 1 << logn;
-  const int G = n >> LOGQ;                // regions per face side
+  const int G = n >> LOGQ;  // blocks per face side
+  const int G2 = G * G;
+  const int FG = p.group_faces;
   const __amdgpu_buffer_rsrc_t src =
       source_resource(static_cast<const SrcT*>(p.src), 6 * (n << logn));
   const float eps = quotient_margin(logn);
   const bool comp = p.comp != 0;
+
+  constexpr int STRIDE = image_stride(Q);
+  constexpr int IMG = Q * STRIDE;
+  float* img = reinterpret_cast<float*>(dyn_lds) + wave * IMG;  // this wave's block image
+  int* lkey = reinterpret_cast<int*>(dyn_lds + kWaves * IMG * 4);
+  float* lval = reinterpret_cast<float*>(lkey + p.listed);
+  double* gS = reinterpret_cast<double*>(dyn_lds + ((kWaves * IMG * 4 + 8 * p.listed + 7) & ~7));
+
   // index row of this vertex: its own, or its cluster's support row
   const int32_t* idx_row = nullptr;
   bool row_valid = true;
@@ -249,108 +307,213 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
     }
   }
   const int nnz = row_valid ? p.nnz : 0;
+  const int listed = row_valid ? p.listed : 0;
 
   // faces touched by this vertex's transport row
+  unsigned m = 0;
+  for (int e = tid; e < nnz; e += kThreads) {
+    const int idx = idx_row ? idx_row[e] : e;
+    if (idx >= 0 && idx < 6 * (n << logn)) m |= 1u << (idx >> (2 * logn));
+  }
   if (tid == 0) face_mask = 0;
   __syncthreads();
-  {
-    unsigned m = 0;
-    for (int e = tid; e < nnz; e += kThreads) {
-      const int idx = idx_row ? idx_row[e] : e;
-      if (idx >= 0 && idx < 6 * (n << logn)) m |= 1u << (idx >> (2 * logn));
-    }
-    if (m) atomicOr(&face_mask, m);
-  }
+  if (m) atomicOr(&face_mask, m);
   __syncthreads();
-  const unsigned faces = face_mask;
-  const bool owns_tile = tid < TS * TS;
+  const unsigned faces = __builtin_amdgcn_readfirstlane(face_mask);
+  const int nf = __popc(faces);
+  const int ngroups = (nf + FG - 1) / FG;
+
+  const bool owns_tile = lane < TS * TS;
+  constexpr int LOGTS = __builtin_ctz(TS);
+  const int ty = lane >> LOGTS, tx = lane & (TS - 1);  // tile of this lane, and its texel in
+                                                        // each TS x TS patch of the gather
+  const uint64_t lanes_below = (uint64_t(1) << lane) - 1;
 
   for (int f = 0; f < p.nframes; ++f) {
-    const IRot R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr);
+    IRot R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R.m[k] = __builtin_amdgcn_readfirstlane(R.m[k]);
     Acc acc = {0.0f, 0.0f};
 
-    for (int face = 0; face < 6; ++face) {
-      if (!((faces >> face) & 1u)) continue;
-      const FaceAxes ax = face_axes(R, face);
+    for (int grp = 0; grp < ngroups; ++grp) {
+      const int g0 = grp * FG;
+      const int nfg = min(FG, nf - g0);
 
-      for (int reg = 0; reg < G * G; ++reg) {
-        const int gy = reg / G, gx = reg - gy * G;
+      if (f == 0 || ngroups > 1) {
+        // List the first `listed` entries by consumer (wave or coarse), in a
+        // fixed order: owner, then entry chunk, wave and lane.
+        const int nchunks = (listed + kThreads - 1) / kThreads;
+        for (int ch = 0; ch < nchunks; ++ch) {
+          const int e = ch * kThreads + tid;
+          int key = 0, owner = -1;
+          if (e < listed) owner = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+#pragma unroll
+          for (int o = 0; o < kOwners; ++o) {
+            const uint64_t b = __ballot(owner == o);
+            if (lane == 0) cnt[ch][wave][o] = __popcll(b);
+          }
+        }
+        __syncthreads();
+        if (tid < kOwners) {
+          // running start of each (chunk, wave) run of owner tid, then totals
+          int run = 0;
+          for (int ch = 0; ch < nchunks; ++ch)
+            for (int w = 0; w < kWaves; ++w) {
+              const int c = cnt[ch][w][tid];
+              cnt[ch][w][tid] = run;
+              run += c;
+            }
+          lcount[tid] = run;
+        }
+        wave_sync();
+        if (tid < kOwners) {
+          int b = 0;
+          for (int o = 0; o < tid; ++o) b += lcount[o];
+          lbase[tid] = b;
+        }
+        __syncthreads();
+        for (int ch = 0; ch < nchunks; ++ch) {
+          const int e = ch * kThreads + tid;
+          int key = 0, owner = -1;
+          if (e < listed) owner = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+          int rank = 0;
+#pragma unroll
+          for (int o = 0; o < kOwners; ++o) {
+            const uint64_t b = __ballot(owner == o);
+            if (owner == o) rank = __popcll(b & lanes_below);
+          }
+          if (owner >= 0) {
+            const int at = lbase[owner] + cnt[ch][wave][owner] + rank;
+            lkey[at] = key;
+            lval[at] = transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e);
+          }
+        }
+        __syncthreads();
+      }
+
+      // Blocks of the group, round-robin over the waves; no barrier inside.
+      const int nblk = nfg * G2;
+      const int my_base = __builtin_amdgcn_readfirstlane(lbase[wave]);
+      const int my_count = __builtin_amdgcn_readfirstlane(lcount[wave]);
+      for (int gi = wave; gi < nblk; gi += kWaves) {
+        const int r = gi / G2, blk = gi - r * G2;
+        const int face = nth_face(faces, g0 + r);
+        const FaceAxes ax = face_axes(R, face);
+        const int by = blk / G, bx = blk - by * G;
+        // Gather in TS x TS patches of adjacent texels (one load instruction
+        // covers a compact patch, which the L1 serves with few cache lines):
+        // lane (ty, tx) takes texel (TS a + ty, TS b + tx) of every patch
+        // (a, b) and stores it raw into the block image.
         if (owns_tile) {
-          const int ty = tid >> LOGTS, tx = tid & (TS - 1);
-          float g[T][T];
-          const int i0 = (gy << LOGQ) + ty * T, j0 = (gx << LOGQ) + tx * T;
+          const int i0 = (by << LOGQ) + ty, j0 = (bx << LOGQ) + tx;
           const int U0 = 2 * j0 + 1 - n, V0 = 2 * i0 + 1 - n;
-          int3 d0;
-          d0.x = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
-          d0.y = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
-          d0.z = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
-          gather_general<T, SrcT>(g, d0, ax, src, logn, eps);
+          int rx = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
+          int ry = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
+          int rz = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            int dx = rx, dy = ry, dz = rz;
+#pragma unroll
+            for (int b = 0; b < T; ++b) {
+              img[(TS * a + ty) * STRIDE + TS * b + tx] =
+                  load_src<SrcT>(src, source_texel(dx, dy, dz, logn, eps));
+              dx = wrap_mad(ax.mU.x, 2 * TS, dx);
+              dy = wrap_mad(ax.mU.y, 2 * TS, dy);
+              dz = wrap_mad(ax.mU.z, 2 * TS, dz);
+            }
+            rx = wrap_mad(ax.mV.x, 2 * TS, rx);
+            ry = wrap_mad(ax.mV.y, 2 * TS, ry);
+            rz = wrap_mad(ax.mV.z, 2 * TS, rz);
+          }
+        }
+        wave_sync();
+        float s = 0.0f;  // unscaled sum of this lane's tile, then of its block
+        if (owns_tile) {
+          // the lane's T x T tile: levels up to side T in registers, in place
+          float g[T][T];
+#pragma unroll
+          for (int rr = 0; rr < T; ++rr)
+#pragma unroll
+            for (int cc = 0; cc < T; ++cc) g[rr][cc] = img[(ty * T + rr) * STRIDE + tx * T + cc];
           tile_levels<T>(g);
 #pragma unroll
-          for (int r = 0; r < T; ++r)
+          for (int rr = 0; rr < T; ++rr)
 #pragma unroll
-            for (int c = 0; c < T; ++c) img[((ty * T + r) << LOGQ) + tx * T + c] = g[r][c];
-          tS[ty * TS + tx] = double(g[0][0]);
+            for (int cc = 0; cc < T; ++cc) img[(ty * T + rr) * STRIDE + tx * T + cc] = g[rr][cc];
+          s = g[0][0];
         }
-        __syncthreads();
-        // levels above the tile, inside the region (FP64 block sums)
+        // levels above the tile, unscaled: the four tiles of a block of side
+        // 2 ht tiles are lanes l, l ^ ht, l ^ ht TS and l ^ (ht TS + ht)
 #pragma unroll
-        for (int Bt = 2; Bt <= TS; Bt <<= 1) {
-          const int nb = TS / Bt, ht = Bt / 2;
-          if (tid < nb * nb) {
-            const int br = tid / nb, bc = tid - br * nb;
-            const int r0 = br * Bt, c0 = bc * Bt;
-            double S, H, V, D;
-            tile_levels_d(tS[r0 * TS + c0], tS[r0 * TS + c0 + ht], tS[(r0 + ht) * TS + c0],
-                          tS[(r0 + ht) * TS + c0 + ht], S, H, V, D);
-            tS[r0 * TS + c0] = S;
-            img[((r0 * T) << LOGQ) + (c0 + ht) * T] = float(H);
-            img[(((r0 + ht) * T) << LOGQ) + c0 * T] = float(V);
-            img[(((r0 + ht) * T) << LOGQ) + (c0 + ht) * T] = float(D);
+        for (int ht = 1; ht < TS; ht <<= 1) {
+          const float b = __shfl_xor(s, ht, 64);
+          const float c = __shfl_xor(s, ht * TS, 64);
+          const float d = __shfl_xor(s, ht * TS + ht, 64);
+          if (owns_tile && ((tx | ty) & (2 * ht - 1)) == 0) {
+            img[(ty * T) * STRIDE + (tx + ht) * T] = (s - b) + (c - d);
+            img[((ty + ht) * T) * STRIDE + tx * T] = (s + b) - (c + d);
+            img[((ty + ht) * T) * STRIDE + (tx + ht) * T] = (s - b) - (c - d);
+            s = (s + b) + (c + d);
           }
-          __syncthreads();
         }
-        if (tid == 0) gS[reg] = tS[0];
-        // entries whose basis function lies inside this region
-        for (int e = tid; e < nnz; e += kThreads) {
-          const int idx = idx_row ? idx_row[e] : e;
-          const Slot s = decode_slot(idx, logn);
-          if (s.face != face || s.logb > LOGQ || (s.pr | s.pc) == 0) continue;
-          if ((s.pr >> LOGQ) != gy || (s.pc >> LOGQ) != gx) continue;
-          const float coef = img[((s.pr & (Q - 1)) << LOGQ) + (s.pc & (Q - 1))];
-          acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e), coef, comp);
+        // the block's orthonormal scaling coefficient, for the levels above
+        if (lane == 0) gS[gi] = double(s) * (1.0 / Q);
+        wave_sync();
+        // listed entries of this block
+        for (int k = lane; k < my_count; k += 64) {
+          const int key = lkey[my_base + k];
+          if (((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
+            acc_add(acc, lval[my_base + k],
+                    ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
         }
-        __syncthreads();
+        // entries past the list
+        for (int e = listed + lane; e < nnz; e += 64) {
+          int key = 0;
+          const int owner = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+          if (owner >= 0 && owner < kWaves && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
+            acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
+                    ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
+        }
+        wave_sync();
       }
-      // levels above the regions (region sums in FP64)
-      if (G > 1 && tid == 0) {
-        for (int Bg = 2; Bg <= G; Bg <<= 1) {
-          const int hg = Bg / 2;
-          for (int r0 = 0; r0 < G; r0 += Bg)
-            for (int c0 = 0; c0 < G; c0 += Bg) {
+      __syncthreads();
+      // levels above the blocks, per face of the group (FP64, in place)
+      if (G > 1 && wave == 0) {
+        for (int r = 0; r < nfg; ++r) {
+          double* gf = gS + r * G2;
+          for (int Bg = 2; Bg <= G; Bg <<= 1) {
+            const int hg = Bg / 2, nb = G / Bg;
+            for (int t = lane; t < nb * nb; t += 64) {
+              const int r0 = (t / nb) * Bg, c0 = (t % nb) * Bg;
               double S, H, V, D;
-              tile_levels_d(gS[r0 * G + c0], gS[r0 * G + c0 + hg], gS[(r0 + hg) * G + c0],
-                            gS[(r0 + hg) * G + c0 + hg], S, H, V, D);
-              gS[r0 * G + c0] = S;
-              gS[r0 * G + c0 + hg] = H;
-              gS[(r0 + hg) * G + c0] = V;
-              gS[(r0 + hg) * G + c0 + hg] = D;
+              tile_levels_d(gf[r0 * G + c0], gf[r0 * G + c0 + hg], gf[(r0 + hg) * G + c0],
+                            gf[(r0 + hg) * G + c0 + hg], S, H, V, D);
+              gf[r0 * G + c0] = S;
+              gf[r0 * G + c0 + hg] = H;
+              gf[(r0 + hg) * G + c0] = V;
+              gf[(r0 + hg) * G + c0 + hg] = D;
             }
+            wave_sync();
+          }
         }
       }
       __syncthreads();
-      for (int e = tid; e < nnz; e += kThreads) {
-        const int idx = idx_row ? idx_row[e] : e;
-        const Slot s = decode_slot(idx, logn);
-        if (s.face != face) continue;
-        if (s.logb <= LOGQ && (s.pr | s.pc) != 0) continue;
-        const float coef = float(gS[(s.pr >> LOGQ) * G + (s.pc >> LOGQ)]);
-        acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e), coef, comp);
+      // coarse entries: blocks wider than Q and the faces' scaling coefficients
+      {
+        const int cb = lbase[kWaves], cn = lcount[kWaves];
+        for (int k = tid; k < cn; k += kThreads)
+          acc_add(acc, lval[cb + k], float(gS[lkey[cb + k]]), comp);
+        for (int e = listed + tid; e < nnz; e += kThreads) {
+          int key = 0;
+          if (classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key) == kWaves)
+            acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
+                    float(gS[key]), comp);
+        }
       }
-      __syncthreads();
     }
 
-    // workgroup reduction
+    // workgroup reduction; its barrier also orders this frame's reads of the
+    // block sums and lists before the next frame's writes
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
       Acc other;
@@ -362,14 +525,14 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         acc.s += other.s;
       }
     }
-    if ((tid & 63) == 0) {
-      red_s[tid >> 6] = acc.s;
-      red_c[tid >> 6] = acc.c;
+    if (lane == 0) {
+      red_s[wave] = acc.s;
+      red_c[wave] = acc.c;
     }
     __syncthreads();
     if (tid == 0) {
       Acc t = {red_s[0], red_c[0]};
-      for (int w = 1; w < kThreads / 64; ++w) {
+      for (int w = 1; w < kWaves; ++w) {
         Acc o = {red_s[w], red_c[w]};
         if (comp) {
           t = acc_merge(t, o);
@@ -379,7 +542,6 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
       }
       p.out[int64_t(f) * p.nvert + v] = comp ? (t.s + t.c) : t.s;
     }
-    __syncthreads();
   }
 }
 
@@ -422,19 +584,23 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
 
 template <int Q, typename SrcT>
 int launch_q(const RelightParams& prm, int64_t nvert, hipStream_t s) {
-  hipLaunchKernelGGL((relight_kernel<Q, SrcT>), dim3(unsigned(nvert)), dim3(kThreads), 0, s, prm);
+  const int G = (1 << prm.logn) / Q;
+  const size_t lds = ((size_t(kWaves) * Q * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) &
+                      ~size_t(7)) +
+                     size_t(prm.group_faces) * G * G * 8;
+  hipLaunchKernelGGL((relight_kernel<Q, SrcT>), dim3(unsigned(nvert)), dim3(kThreads), lds, s,
+                     prm);
   return check_launch("relight_kernel");
 }
 
 template <typename SrcT>
 int launch_src(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
-  switch (n < kMaxRegion ? n : kMaxRegion) {
+  switch (n < kBlock ? n : kBlock) {
     case 2: return launch_q<2, SrcT>(prm, nvert, s);
     case 4: return launch_q<4, SrcT>(prm, nvert, s);
     case 8: return launch_q<8, SrcT>(prm, nvert, s);
     case 16: return launch_q<16, SrcT>(prm, nvert, s);
-    case 32: return launch_q<32, SrcT>(prm, nvert, s);
-    default: return launch_q<kMaxRegion, SrcT>(prm, nvert, s);
+    default: return launch_q<kBlock, SrcT>(prm, nvert, s);
   }
 }
 
@@ -458,6 +624,10 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   p.logn = ilog2(a.n);
   p.dtype = a.t_dtype;
   p.comp = (a.flags & RRT_COMPENSATED) ? 1 : 0;
+  p.listed = a.nnz < kMaxListed ? a.nnz : kMaxListed;
+  const int G = a.n < kBlock ? 1 : a.n / kBlock;
+  const int fit = kGroupBytes / (G * G * 8);
+  p.group_faces = fit < 1 ? 1 : (fit > 6 ? 6 : fit);
   return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, s) : launch_src<float>(p, a.n, a.nvert, s);
 }
 
