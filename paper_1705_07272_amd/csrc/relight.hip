@@ -410,13 +410,15 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
           int rx = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
           int ry = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
           int rz = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
+          // all T^2 loads are issued before the first store, so that they
+          // are in flight together
+          float val[T][T];
 #pragma unroll
           for (int a = 0; a < T; ++a) {
             int dx = rx, dy = ry, dz = rz;
 #pragma unroll
             for (int b = 0; b < T; ++b) {
-              img[(TS * a + ty) * STRIDE + TS * b + tx] =
-                  load_src<SrcT>(src, source_texel(dx, dy, dz, logn, eps));
+              val[a][b] = load_src<SrcT>(src, source_texel(dx, dy, dz, logn, eps));
               dx = wrap_mad(ax.mU.x, 2 * TS, dx);
               dy = wrap_mad(ax.mU.y, 2 * TS, dy);
               dz = wrap_mad(ax.mU.z, 2 * TS, dz);
@@ -425,6 +427,10 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             ry = wrap_mad(ax.mV.y, 2 * TS, ry);
             rz = wrap_mad(ax.mV.z, 2 * TS, rz);
           }
+#pragma unroll
+          for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
         }
         wave_sync();
         float s = 0.0f;  // unscaled sum of this lane's tile, then of its block
