@@ -333,7 +333,7 @@ def main():
     achieved = texels * OPS_PER_TEXEL / (ms_kernel * 1e-3) / 1e12
 
     traffic = None
-    prof = os.path.join(ROOT, "profiles", f"relight_{w.name}_{args.form}_hbm.json")
+    prof = os.path.join(ROOT, "profiles", f"relight_{w.name}_{args.form}_hbm.txt")
     if os.path.exists(prof):
         with open(prof) as fh:
             rec = json.load(fh)
