@@ -103,7 +103,11 @@ int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t count, void* 
  *   x [rows][len] float32; idx [rows][k] int32 and val [rows][k] float32
  *   receive the kept positions in ascending order and their values.
  *   Ties in |x| go to the lower position.  NaN inputs: unspecified choice.
- *   0 <= k <= len, len < 2^31.  Workspace: rrt_topk_workspace() bytes.
+ *   0 <= k <= len, len < 2^31.  Workspace: rrt_topk_workspace() bytes,
+ *   256-byte aligned: zero except for at most 8 rows of at least 16384
+ *   values with k < len (per-chunk histograms and a candidate list, about
+ *   8 len + 1 MiB bytes per row); too small a workspace is
+ *   RRT_ERR_WORKSPACE.
  * --------------------------------------------------------------------- */
 int rrt_topk_workspace(int64_t rows, int64_t len, int k, size_t* bytes);
 int rrt_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val,

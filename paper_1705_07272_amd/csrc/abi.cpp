@@ -133,20 +133,23 @@ int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t count, void* 
 int rrt_topk_workspace(int64_t rows, int64_t len, int k, size_t* bytes) {
   if (!bytes) return fail(RRT_ERR_INVALID, "topk_workspace: null bytes");
   if (rows < 0 || len < 0 || k < 0 || k > len) return fail(RRT_ERR_INVALID, "topk_workspace: bad sizes");
-  *bytes = 0;
+  *bytes = topk_workspace_bytes(rows, len, k);
   return RRT_OK;
 }
 
 int rrt_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val, void* ws,
              size_t ws_bytes, void* stream) {
-  (void)ws;
-  (void)ws_bytes;
   if (rows < 0 || rows > int64_t(0x7fffffff)) return fail(RRT_ERR_INVALID, "topk: rows=%lld out of range", (long long)rows);
   if (len < 0 || len >= (int64_t(1) << 31)) return fail(RRT_ERR_INVALID, "topk: len=%lld out of range", (long long)len);
   if (k < 0 || k > len) return fail(RRT_ERR_INVALID, "topk: k=%d not in [0,len=%lld]", k, (long long)len);
   if (rows == 0 || k == 0) return RRT_OK;
   if (!x || !idx || !val) return fail(RRT_ERR_INVALID, "topk: null pointer");
-  return launch_topk(x, rows, len, k, idx, val, static_cast<hipStream_t>(stream));
+  const size_t need = topk_workspace_bytes(rows, len, k);
+  if (need) {
+    const int st = check_ws(ws, ws_bytes, need, "topk");
+    if (st) return st;
+  }
+  return launch_topk(x, rows, len, k, idx, val, ws, static_cast<hipStream_t>(stream));
 }
 
 int rrt_haar_phase_shift_workspace(int n, int nrot, size_t* bytes) {

@@ -31,8 +31,9 @@ int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int 
                             hipStream_t s);
 
 // Selection (topk.hip).
+size_t topk_workspace_bytes(int64_t rows, int64_t len, int k);
 int launch_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val,
-                hipStream_t s);
+                void* ws, hipStream_t s);
 
 // Coefficient scatter into a zeroed dense map (relight.hip).
 int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n,

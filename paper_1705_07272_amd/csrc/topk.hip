@@ -151,11 +151,363 @@ __global__ __launch_bounds__(kThreads) void topk_rows(const float* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// A few long rows (one environment map): the row is split into chunks
+// processed by many workgroups.
+//   1. per-chunk histograms of the top 12 key bits;
+//   2. per row: the bin holding the k-th largest key and, per chunk, the
+//      start of that bin's keys in a candidate list;
+//   3. per chunk: the candidates, compacted in position order;
+//   4. per row: radix select over the candidates' remaining 19 bits gives the
+//      exact threshold key t and how many keys equal to t are kept; the
+//      position of the last kept one is the cut;
+//   5. per chunk: the number of kept entries (key > t, or key == t at a
+//      position up to the cut);
+//   6. per chunk: ordered emission at the sum of the preceding chunks' counts.
+// ---------------------------------------------------------------------------
+constexpr int kBinBits = 12;
+constexpr int kBins = 1 << kBinBits;
+constexpr int kLowBits = 31 - kBinBits;  // key bits below the bin
+constexpr int kMaxChunks = 64;
+constexpr int kMinChunk = 4096;
+constexpr int kChunkThreads = 256;
+constexpr int kRowThreads = 1024;
+
+// Per-row parameters in the workspace.
+enum { P_BIN, P_NEED, P_CAND, P_THR, P_CUT, P_COUNT };
+
+struct ChunkPlan {
+  int chunks;
+  int64_t chunk_len;
+};
+
+ChunkPlan chunk_plan(int64_t len) {
+  int64_t chunks = (len + kMinChunk - 1) / kMinChunk;
+  if (chunks > kMaxChunks) chunks = kMaxChunks;
+  ChunkPlan c;
+  c.chunks = int(chunks);
+  c.chunk_len = (len + chunks - 1) / chunks;
+  return c;
+}
+
+struct TopkWs {
+  uint32_t* hist;     // [rows][chunks][kBins]
+  uint32_t* eq_base;  // [rows][chunks]
+  uint32_t* sel_cnt;  // [rows][chunks]
+  uint32_t* par;      // [rows][P_COUNT]
+  uint32_t* ckey;     // [rows][len]
+  int32_t* cidx;      // [rows][len]
+};
+
+size_t carve(void* base, int64_t rows, int64_t len, TopkWs* w) {
+  const ChunkPlan cp = chunk_plan(len);
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = p ? p + off : nullptr;
+    off += align256(bytes);
+    return q;
+  };
+  TopkWs t;
+  t.hist = reinterpret_cast<uint32_t*>(take(size_t(rows) * cp.chunks * kBins * 4));
+  t.eq_base = reinterpret_cast<uint32_t*>(take(size_t(rows) * cp.chunks * 4));
+  t.sel_cnt = reinterpret_cast<uint32_t*>(take(size_t(rows) * cp.chunks * 4));
+  t.par = reinterpret_cast<uint32_t*>(take(size_t(rows) * P_COUNT * 4));
+  t.ckey = reinterpret_cast<uint32_t*>(take(size_t(rows) * len * 4));
+  t.cidx = reinterpret_cast<int32_t*>(take(size_t(rows) * len * 4));
+  if (w) *w = t;
+  return off;
+}
+
+// Sum over the workgroup; every thread gets the total.
+template <int kWaves>
+__device__ __forceinline__ int block_sum(int x, int* sh) {
+  int total;
+  block_scan<kWaves>(x, &total, sh);
+  return total;
+}
+
+__global__ __launch_bounds__(kChunkThreads) void tk_hist(const float* __restrict__ x, int64_t len,
+                                                         int64_t chunk_len, int chunks,
+                                                         uint32_t* __restrict__ hist) {
+  __shared__ unsigned h[kBins];
+  const int tid = threadIdx.x, c = blockIdx.x, row = blockIdx.y;
+  for (int b = tid; b < kBins; b += kChunkThreads) h[b] = 0;
+  __syncthreads();
+  const float* r = x + int64_t(row) * len;
+  const int64_t lo = int64_t(c) * chunk_len;
+  const int64_t hi = lo + chunk_len < len ? lo + chunk_len : len;
+  int64_t i = lo + tid;
+  for (; i + 3 * kChunkThreads < hi; i += 4 * kChunkThreads) {
+    float v4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v4[j] = r[i + j * kChunkThreads];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) atomicAdd(&h[key_of(v4[j]) >> kLowBits], 1u);
+  }
+  for (; i < hi; i += kChunkThreads) atomicAdd(&h[key_of(r[i]) >> kLowBits], 1u);
+  __syncthreads();
+  uint32_t* out = hist + (int64_t(row) * chunks + c) * kBins;
+  for (int b = tid; b < kBins; b += kChunkThreads) out[b] = h[b];
+}
+
+__global__ __launch_bounds__(kRowThreads) void tk_bin(const uint32_t* __restrict__ hist,
+                                                      int chunks, int k,
+                                                      uint32_t* __restrict__ eq_base,
+                                                      uint32_t* __restrict__ par) {
+  constexpr int kWaves = kRowThreads / 64;
+  constexpr int kPer = kBins / kRowThreads;
+  __shared__ int sh[kWaves];
+  __shared__ int s_bin, s_need;
+  const int tid = threadIdx.x, row = blockIdx.x;
+  if (tid == 0) {
+    s_bin = 0;
+    s_need = 0;
+  }
+  const uint32_t* h = hist + int64_t(row) * chunks * kBins;
+  unsigned tot[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) tot[j] = 0;
+  for (int c = 0; c < chunks; ++c)
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) tot[j] += h[int64_t(c) * kBins + kPer * tid + j];
+  int mine = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) mine += int(tot[j]);
+  int total;
+  const int before = block_scan<kWaves>(mine, &total, sh);
+  // keys in bins above this thread's bins
+  unsigned above = unsigned(total - before - mine);
+#pragma unroll
+  for (int j = kPer - 1; j >= 0; --j) {
+    if (above < unsigned(k) && above + tot[j] >= unsigned(k)) {
+      s_bin = kPer * tid + j;
+      s_need = int(unsigned(k) - above);
+    }
+    above += tot[j];
+  }
+  __syncthreads();
+  const int bin = s_bin;
+  // start of each chunk's candidates (keys in the bin), in chunk order
+  if (tid < 64) {
+    int run = 0;
+    for (int c0 = 0; c0 < chunks; c0 += 64) {
+      const int c = c0 + tid;
+      const int cnt = c < chunks ? int(h[int64_t(c) * kBins + bin]) : 0;
+      int v = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (tid >= o) v += t;
+      }
+      if (c < chunks) eq_base[int64_t(row) * chunks + c] = unsigned(run + v - cnt);
+      run += __shfl(v, 63, 64);
+    }
+    if (tid == 0) {
+      uint32_t* pr = par + int64_t(row) * P_COUNT;
+      pr[P_BIN] = unsigned(bin);
+      pr[P_NEED] = unsigned(s_need);
+      pr[P_CAND] = unsigned(run);
+    }
+  }
+}
+
+// Ordered compaction helper: the keep flags of kItems consecutive positions
+// per thread become positions base + rank in position order.
+template <int kThreads, typename Pred, typename Emit>
+__device__ __forceinline__ int ordered_pass(int64_t lo, int64_t hi, int base, int* sh, Pred keep,
+                                            Emit emit) {
+  constexpr int kWaves = kThreads / 64;
+  for (int64_t c0 = lo; c0 < hi; c0 += int64_t(kThreads) * kItems) {
+    unsigned sel = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + int64_t(threadIdx.x) * kItems + j;
+      if (i < hi && keep(i)) sel |= 1u << j;
+    }
+    int total;
+    int pos = base + block_scan<kWaves>(__popc(sel), &total, sh);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      if (sel & (1u << j)) emit(c0 + int64_t(threadIdx.x) * kItems + j, pos++);
+    }
+    base += total;
+  }
+  return base;
+}
+
+__global__ __launch_bounds__(kChunkThreads) void tk_cand(const float* __restrict__ x, int64_t len,
+                                                         int64_t chunk_len, int chunks,
+                                                         const uint32_t* __restrict__ eq_base,
+                                                         const uint32_t* __restrict__ par,
+                                                         uint32_t* __restrict__ ckey,
+                                                         int32_t* __restrict__ cidx) {
+  __shared__ int sh[kChunkThreads / 64];
+  const int c = blockIdx.x, row = blockIdx.y;
+  const float* r = x + int64_t(row) * len;
+  const unsigned bin = par[int64_t(row) * P_COUNT + P_BIN];
+  const int64_t lo = int64_t(c) * chunk_len;
+  const int64_t hi = lo + chunk_len < len ? lo + chunk_len : len;
+  uint32_t* kk = ckey + int64_t(row) * len;
+  int32_t* ki = cidx + int64_t(row) * len;
+  ordered_pass<kChunkThreads>(
+      lo, hi, int(eq_base[int64_t(row) * chunks + c]), sh,
+      [&](int64_t i) { return (key_of(r[i]) >> kLowBits) == bin; },
+      [&](int64_t i, int pos) {
+        kk[pos] = key_of(r[i]);
+        ki[pos] = int32_t(i);
+      });
+}
+
+__global__ __launch_bounds__(kRowThreads) void tk_resolve(int64_t len,
+                                                          const uint32_t* __restrict__ ckey,
+                                                          const int32_t* __restrict__ cidx,
+                                                          uint32_t* __restrict__ par) {
+  constexpr int kWaves = kRowThreads / 64;
+  __shared__ unsigned h[1024];
+  __shared__ int sh[kWaves];
+  __shared__ unsigned s_prefix, s_need;
+  __shared__ int s_cut;
+  const int tid = threadIdx.x, row = blockIdx.x;
+  uint32_t* pr = par + int64_t(row) * P_COUNT;
+  const int m = int(pr[P_CAND]);
+  const uint32_t* kk = ckey + int64_t(row) * len;
+  const int32_t* ki = cidx + int64_t(row) * len;
+  unsigned prefix = pr[P_BIN] << kLowBits;
+  unsigned mask = ~((1u << kLowBits) - 1u) & 0x7fffffffu;
+  unsigned need = pr[P_NEED];
+  // two passes: bits 18..9 (1024 bins), then bits 8..0 (512 bins)
+  for (int pass = 0; pass < 2; ++pass) {
+    const int shift = pass == 0 ? 9 : 0;
+    const int nb = pass == 0 ? 1024 : 512;
+    if (tid == 0) {
+      s_prefix = prefix;
+      s_need = need;
+    }
+    h[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < m; i += kRowThreads) {
+      const unsigned u = kk[i];
+      if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & unsigned(nb - 1)], 1u);
+    }
+    __syncthreads();
+    // bin b = tid: keys above it, from the top
+    const int mine = tid < nb ? int(h[tid]) : 0;
+    int total;
+    const int before = block_scan<kWaves>(mine, &total, sh);
+    const unsigned above = unsigned(total - before - mine);
+    if (tid < nb && above < need && above + unsigned(mine) >= need) {
+      s_prefix = prefix | (unsigned(tid) << shift);
+      s_need = need - above;
+    }
+    __syncthreads();
+    prefix = s_prefix;
+    need = s_need;
+    mask |= unsigned(nb - 1) << shift;
+    __syncthreads();
+  }
+  // the need-th key equal to the threshold, in position order
+  if (tid == 0) s_cut = -1;
+  __syncthreads();
+  int base = 0;
+  for (int c0 = 0; c0 < m && base < int(need); c0 += kRowThreads) {
+    const int i = c0 + tid;
+    const int eq = (i < m && kk[i] == prefix) ? 1 : 0;
+    int total;
+    const int rank = base + block_scan<kWaves>(eq, &total, sh);
+    if (eq && rank == int(need) - 1) s_cut = ki[i];
+    base += total;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    pr[P_THR] = prefix;
+    pr[P_CUT] = unsigned(s_cut);
+  }
+}
+
+__device__ __forceinline__ bool kept(float v, int64_t i, unsigned thr, int cut) {
+  const unsigned u = key_of(v);
+  return u > thr || (u == thr && i <= int64_t(cut));
+}
+
+__global__ __launch_bounds__(kChunkThreads) void tk_count(const float* __restrict__ x, int64_t len,
+                                                          int64_t chunk_len, int chunks,
+                                                          const uint32_t* __restrict__ par,
+                                                          uint32_t* __restrict__ sel_cnt) {
+  __shared__ int sh[kChunkThreads / 64];
+  const int c = blockIdx.x, row = blockIdx.y;
+  const float* r = x + int64_t(row) * len;
+  const unsigned thr = par[int64_t(row) * P_COUNT + P_THR];
+  const int cut = int(par[int64_t(row) * P_COUNT + P_CUT]);
+  const int64_t lo = int64_t(c) * chunk_len;
+  const int64_t hi = lo + chunk_len < len ? lo + chunk_len : len;
+  int n = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kChunkThreads) n += kept(r[i], i, thr, cut);
+  n = block_sum<kChunkThreads / 64>(n, sh);
+  if (threadIdx.x == 0) sel_cnt[int64_t(row) * chunks + c] = unsigned(n);
+}
+
+__global__ __launch_bounds__(kChunkThreads) void tk_emit(const float* __restrict__ x, int64_t len,
+                                                         int64_t chunk_len, int chunks, int k,
+                                                         const uint32_t* __restrict__ par,
+                                                         const uint32_t* __restrict__ sel_cnt,
+                                                         int32_t* __restrict__ oidx,
+                                                         float* __restrict__ oval) {
+  __shared__ int sh[kChunkThreads / 64];
+  const int c = blockIdx.x, row = blockIdx.y;
+  const float* r = x + int64_t(row) * len;
+  const unsigned thr = par[int64_t(row) * P_COUNT + P_THR];
+  const int cut = int(par[int64_t(row) * P_COUNT + P_CUT]);
+  const int64_t lo = int64_t(c) * chunk_len;
+  const int64_t hi = lo + chunk_len < len ? lo + chunk_len : len;
+  int before = 0;
+  for (int c2 = threadIdx.x; c2 < c; c2 += kChunkThreads)
+    before += int(sel_cnt[int64_t(row) * chunks + c2]);
+  before = block_sum<kChunkThreads / 64>(before, sh);
+  int32_t* ri = oidx + int64_t(row) * k;
+  float* rv = oval + int64_t(row) * k;
+  ordered_pass<kChunkThreads>(
+      lo, hi, before, sh, [&](int64_t i) { return kept(r[i], i, thr, cut); },
+      [&](int64_t i, int pos) {
+        if (pos < k) {
+          ri[pos] = int32_t(i);
+          rv[pos] = r[i];
+        }
+      });
+}
+
+bool use_chunks(int64_t rows, int64_t len, int k) {
+  return rows <= 8 && len >= 16384 && int64_t(k) < len;
+}
+
 }  // namespace
 
+size_t topk_workspace_bytes(int64_t rows, int64_t len, int k) {
+  return use_chunks(rows, len, k) ? carve(nullptr, rows, len, nullptr) : 0;
+}
+
 int launch_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, float* val,
-                hipStream_t s) {
+                void* ws, hipStream_t s) {
   if (rows == 0 || k == 0) return RRT_OK;
+  if (use_chunks(rows, len, k)) {
+    TopkWs w;
+    carve(ws, rows, len, &w);
+    const ChunkPlan cp = chunk_plan(len);
+    const dim3 grid(unsigned(cp.chunks), unsigned(rows));
+    hipLaunchKernelGGL(tk_hist, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
+                       w.hist);
+    hipLaunchKernelGGL(tk_bin, dim3(unsigned(rows)), dim3(kRowThreads), 0, s, w.hist, cp.chunks, k,
+                       w.eq_base, w.par);
+    hipLaunchKernelGGL(tk_cand, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
+                       w.eq_base, w.par, w.ckey, w.cidx);
+    hipLaunchKernelGGL(tk_resolve, dim3(unsigned(rows)), dim3(kRowThreads), 0, s, len, w.ckey,
+                       w.cidx, w.par);
+    hipLaunchKernelGGL(tk_count, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
+                       w.par, w.sel_cnt);
+    hipLaunchKernelGGL(tk_emit, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
+                       k, w.par, w.sel_cnt, idx, val);
+    return check_launch("topk chunks");
+  }
   if (rows < 64 && len >= 16384) {
     hipLaunchKernelGGL(topk_rows<1024>, dim3(unsigned(rows)), dim3(1024), 0, s, x, len, k, idx,
                        val);

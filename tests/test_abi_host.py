@@ -66,6 +66,17 @@ def test_topk_validation(rrt):
     assert lib.rrt_topk(_p(0), 1, 10, 3, _p(8), _p(8), None, 0, None) == E.RRT_ERR_INVALID
     assert lib.rrt_topk(_p(0), 0, 10, 3, _p(0), _p(0), None, 0, None) == E.RRT_OK
     assert lib.rrt_topk(_p(0), 4, 10, 0, _p(0), _p(0), None, 0, None) == E.RRT_OK
+    # a few long rows take the chunked selection, which needs a workspace
+    assert lib.rrt_topk_workspace(1, 98304, 1024, ctypes.byref(nb)) == E.RRT_OK
+    need = nb.value
+    assert need >= 2 * 4 * 98304
+    assert lib.rrt_topk_workspace(9, 98304, 1024, ctypes.byref(nb)) == E.RRT_OK and nb.value == 0
+    assert lib.rrt_topk_workspace(1, 98304, 98304, ctypes.byref(nb)) == E.RRT_OK and nb.value == 0
+    assert lib.rrt_topk(_p(256), 1, 98304, 1024, _p(256), _p(256), None, 0, None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_topk(_p(256), 1, 98304, 1024, _p(256), _p(256), _p(256), need - 1,
+                        None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_topk(_p(256), 1, 98304, 1024, _p(256), _p(256), _p(260), need,
+                        None) == E.RRT_ERR_INVALID
 
 
 def test_phase_shift_validation(rrt):

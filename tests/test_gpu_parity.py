@@ -66,7 +66,9 @@ def test_haar_forward_inverse(rrt, n, count):
 
 # ---------------------------------------------------------------- selection (a2)
 @pytest.mark.parametrize("rows,length,k", [(1, 1, 1), (3, 5, 2), (2, 1000, 7), (4, 1025, 1025),
-                                           (1, 98304, 1024), (5, 6144, 256), (2, 3000, 0)])
+                                           (1, 98304, 1024), (5, 6144, 256), (2, 3000, 0),
+                                           (2, 20000, 1), (3, 16384, 16383), (1, 300001, 5000),
+                                           (8, 24576, 2048), (9, 16384, 100)])
 def test_topk_exact(rrt, rows, length, k):
     from oracle.select import topk_abs
     rng = np.random.default_rng(rows * 7 + length)
@@ -80,6 +82,24 @@ def test_topk_exact(rrt, rows, length, k):
         want = topk_abs(x[r], k)
         assert idx[r].tolist() == want.tolist()
         assert np.array_equal(val[r].view(np.uint32), x[r][want].view(np.uint32))
+
+
+@pytest.mark.parametrize("case", ["constant", "few_levels"])
+def test_topk_long_row_ties(rrt, case):
+    """Long rows (the chunked selection) whose threshold falls inside a run of
+    equal magnitudes: the kept equal keys are the lowest positions."""
+    from oracle.select import topk_abs
+    rng = np.random.default_rng(11)
+    length, k = 40000, 3000
+    if case == "constant":
+        x = np.where(rng.random(length) < 0.5, -1.5, 1.5).astype(np.float32)
+    else:
+        x = rng.choice(np.array([0.25, -0.5, 1.0, -2.0], np.float32), size=length)
+    x = x.reshape(1, -1)
+    idx, val = rrt.topk(dev(x), k)
+    want = topk_abs(x[0], k)
+    assert idx.cpu().numpy()[0].tolist() == want.tolist()
+    assert np.array_equal(val.cpu().numpy()[0].view(np.uint32), x[0][want].view(np.uint32))
 
 
 # ---------------------------------------------------------------- storage forms (a7)
