@@ -134,36 +134,49 @@ __device__ __forceinline__ int source_texel_exact(int x, int y, int z, int logn)
 // The same map, with a binary32 fast path on the cube-map instructions
 // (v_cubeid / v_cubesc / v_cubetc / v_cubema: face, in-face coordinates and
 // twice the major component, in the face convention above, ties resolved
-// towards z then y).
+// towards z then y), returned scaled by 2^ES (a byte offset for elements of
+// 2^ES bytes).
 //
-// The components are converted to binary32 (relative error 2^-24 each) and
-// q = h sc / D + h + eps is estimated as fma(sc, n rcp(|ma|), h + eps); as
-// for the exact form its error is below h 2^-21 < eps.  If frac(q) >= 2 eps
+// The components are converted to binary32 (relative error 2^-24 each; sc
+// and D are copies of them, |ma| = 2 D exactly) and q = h sc / D + h + eps
+// is estimated as fma(sc, n rcp(|ma|), h + eps): sc / D is off by at most
+// 2^-23 relative, v_rcp_f32 by one ulp (2^-23), so the product is within
+// h 2^-22 of h sc / D, and the fma rounds once (at most h 2^-23): the error
+// is below 1.5 h 2^-22 < eps = h 2^-20 (quotient_margin).  If frac(q) >= 2 eps
 // for both coordinates, the exact quotient lies strictly between the same
 // two integers as q - eps, so trunc(q) is the exact floor (and lies in
-// [0, n - 1]); otherwise the exact form decides.
+// [0, n - 1]); otherwise the exact form replaces the result.
 //
 // A face chosen by the binary32 comparison that differs from the exact one
 // (a near tie |d_a| ~ |d_b| or an exact tie broken the other way) is always
 // caught: the exact major component then appears as an in-face coordinate
-// with |a_f| / |b_f| in [1 - 2^-23, 1], so that coordinate's q is within
-// h 2^-21 + eps of 0 or 2h and fails the margin test.  A zero direction gives
-// NaN and also takes the exact form.  Every output is in [0, 6 n^2).
-__device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
+// with |a_f| / |b_f| in [1 - 2^-23, 1], so that coordinate's q - eps is
+// within h 2^-23 + 1.5 h 2^-22 = h 2^-21 < eps of 0 or 2h and fails the
+// margin test.  A zero direction gives NaN and also takes the exact form.
+// Every output is in [0, 6 n^2) << ES.
+template <int ES>
+__device__ __forceinline__ unsigned source_texel_scaled(int x, int y, int z, int logn, float eps) {
   const float fx = float(x), fy = float(y), fz = float(z);
   const float hr = float(1 << logn) * __builtin_amdgcn_rcpf(fabsf(__builtin_amdgcn_cubema(fx, fy, fz)));
   const float off = float(1 << (logn - 1)) + eps;
   const float qs = __builtin_fmaf(__builtin_amdgcn_cubesc(fx, fy, fz), hr, off);
   const float qt = __builtin_fmaf(__builtin_amdgcn_cubetc(fx, fy, fz), hr, off);
   const float es = __builtin_amdgcn_fractf(qs), et = __builtin_amdgcn_fractf(qt);
-  if (!(fminf(es, et) >= 2.0f * eps)) return source_texel_exact(x, y, z, logn);
-  const int face = int(__builtin_amdgcn_cubeid(fx, fy, fz));
-  return (face << (2 * logn)) + (int(qt) << logn) + int(qs);
+  // ((face n + i) n + j) << ES
+  const unsigned face = unsigned(int(__builtin_amdgcn_cubeid(fx, fy, fz)));
+  const unsigned row = (unsigned(int(qs)) << ES) + (face << (2 * logn + ES));
+  unsigned at = unsigned(int(qt)) * (unsigned(1) << (logn + ES)) + row;
+  if (!(fminf(es, et) >= 2.0f * eps)) at = unsigned(source_texel_exact(x, y, z, logn)) << ES;
+  return at;
+}
+
+__device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
+  return int(source_texel_scaled<0>(x, y, z, logn, eps));
 }
 
 // Margin of the binary32 quotient estimate (see source_texel).
 __device__ __forceinline__ float quotient_margin(int logn) {
-  return float(1 << (logn - 1)) * 0x1p-19f;
+  return float(1 << (logn - 1)) * 0x1p-20f;
 }
 
 }  // namespace rrt

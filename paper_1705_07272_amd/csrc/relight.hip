@@ -57,15 +57,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const SrcT* p,
                                            count * int(sizeof(SrcT)), kBufferWord3);
 }
 
+// Element of the source map at byte offset `at`.
 template <typename SrcT>
-__device__ __forceinline__ float load_src(__amdgpu_buffer_rsrc_t r, int i);
+__device__ __forceinline__ float load_src(__amdgpu_buffer_rsrc_t r, unsigned at);
 template <>
-__device__ __forceinline__ float load_src<float>(__amdgpu_buffer_rsrc_t r, int i) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
+__device__ __forceinline__ float load_src<float>(__amdgpu_buffer_rsrc_t r, unsigned at) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, int(at), 0, 0));
 }
 template <>
-__device__ __forceinline__ float load_src<__half>(__amdgpu_buffer_rsrc_t r, int i) {
-  const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0);
+__device__ __forceinline__ float load_src<__half>(__amdgpu_buffer_rsrc_t r, unsigned at) {
+  const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, int(at), 0, 0);
   return __half2float(__ushort_as_half(b));
 }
 
@@ -418,7 +419,8 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             int dx = rx, dy = ry, dz = rz;
 #pragma unroll
             for (int b = 0; b < T; ++b) {
-              val[a][b] = load_src<SrcT>(src, source_texel(dx, dy, dz, logn, eps));
+              val[a][b] = load_src<SrcT>(
+                  src, source_texel_scaled<sizeof(SrcT) == 4 ? 2 : 1>(dx, dy, dz, logn, eps));
               dx = wrap_mad(ax.mU.x, 2 * TS, dx);
               dy = wrap_mad(ax.mU.y, 2 * TS, dy);
               dz = wrap_mad(ax.mU.z, 2 * TS, dz);
