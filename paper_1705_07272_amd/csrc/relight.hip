@@ -11,19 +11,18 @@
 // source map reconstructed once per lighting.  The coarser levels are the
 // paper's recursive averaging, done as in-place 2x2 butterflies.
 //
-// Work decomposition (one 256-thread workgroup per vertex, all frames):
-//   * only the faces touched by the vertex's transport row are processed;
-//   * a face is processed in Q x Q regions (Q = min(n, 64)); each of the
-//     16 x 16 threads owns a T x T tile (T = Q / 16): it computes T^2 source
-//     indices (incremental along a row, d += 2 R e_U), gathers the source
-//     texels (L2-resident map) and runs the tile's levels in registers;
-//   * tile results go to an in-place LDS image of the region (coefficient of
-//     a block of side B at its corner offset by B/2 for H/V/D); the levels
-//     above the tile run on the 16 x 16 tile sums in FP64 in LDS, and the
-//     levels above the region on the region sums (FP64);
-//   * the transport row is matched against the LDS image (each entry's Mallat
-//     index maps to one in-place position); products are accumulated per
-//     thread and reduced across the workgroup with wave shuffles.
+// Work decomposition (one wave per vertex, all frames; no workgroup barrier):
+//   * the faces touched by the vertex's transport row are processed, each as
+//     G x G blocks of Q x Q texels (Q = min(n, 32));
+//   * per block, lane (ty, tx) gathers texel (8a + ty, 8b + tx) of each 8 x 8
+//     patch (a compact patch per load instruction) into an LDS image, then
+//     runs the levels of its own 4 x 4 tile in registers and the levels up to
+//     the block with lane shuffles, in place (the coefficient of a block of
+//     side B at its corner offset by B/2 for H/V/D);
+//   * the transport entries are decoded once per vertex into an LDS list; the
+//     entries inside the block read the image, the coarser ones read the FP64
+//     block-sum grid after the levels above the blocks; products are
+//     accumulated per lane and reduced with lane shuffles.
 #include <hip/hip_fp16.h>
 
 #include "geometry.h"
@@ -32,19 +31,15 @@
 namespace rrt {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-// Block side of one wave's unit of work: a 32 x 32 block is 8 x 8 tiles of
-// 4 x 4 texels, one tile per lane, so every Haar level up to the block stays
-// inside the wave (registers, then lane shuffles) and needs no barrier.
+constexpr int kThreads = 64;  // one wave per vertex
+// Block side: a 32 x 32 block is 8 x 8 tiles of 4 x 4 texels, one tile per
+// lane, so every Haar level up to the block stays inside the wave.
 constexpr int kBlock = 32;
-// Transport entries of a vertex listed in LDS (bucketed by consuming wave);
-// entries past this count are decoded from global memory in every block.
-constexpr int kMaxListed = 2048;
-constexpr int kMaxChunks = kMaxListed / kThreads;
+// Transport entries of a vertex listed in LDS; entries past this count are
+// decoded from global memory in every block.
+constexpr int kMaxListed = 512;
 // LDS for the FP64 block sums of the faces processed together.
-constexpr int kGroupBytes = 16384;
-constexpr int kOwners = kWaves + 1;  // one entry list per wave, one for coarse entries
+constexpr int kGroupBytes = 4096;
 
 // Gathers from the source map go through a raw buffer resource: 32-bit
 // offsets (no 64-bit address arithmetic per texel) and hardware range
@@ -238,12 +233,11 @@ __device__ __forceinline__ int nth_face(unsigned faces, int k) {
 // Where a transport entry is consumed when the faces of rank [g0, g0 + FG)
 // among `faces` are processed together.  Block gi = (face rank - g0) G^2 +
 // block row * G + block column holds every coefficient of a block at most Q
-// wide except the face's scaling coefficient; those go to the wave
-// gi mod kWaves, keyed by their block side, gi and position in the block
-// image (the image holds unscaled coefficients).  The
-// others (blocks wider than Q, and the face's scaling coefficient) are
-// "coarse": owner kWaves, key = index of the group's in-place block-sum
-// grid.  Returns -1 for entries outside the group or invalid indices.
+// wide except the face's scaling coefficient: returns 0, key = block side,
+// gi and position in the block image (which holds unscaled coefficients).
+// The others (blocks wider than Q, and the face's scaling coefficient) are
+// "coarse": returns 1, key = index of the group's in-place block-sum grid.
+// Returns -1 for entries outside the group or invalid indices.
 template <int Q>
 __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces, int g0, int FG,
                                         int& key) {
@@ -256,27 +250,24 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
   const int gi = rank * G * G + (s.pr >> LOGQ) * G + (s.pc >> LOGQ);
   if (s.logb <= LOGQ && (s.pr | s.pc) != 0) {
     key = (s.logb << kLogbShift) | (gi << kOffBits) | ((s.pr & (Q - 1)) * STRIDE + (s.pc & (Q - 1)));
-    return gi & (kWaves - 1);
+    return 0;
   }
   key = gi;
-  return kWaves;
+  return 1;
 }
 
-// Q: block side (min(n, kBlock)); a wave's TS x TS lanes each own a T x T tile.
+// Q: block side (min(n, kBlock)); the wave's TS x TS lanes each own a T x T tile.
 template <int Q, typename SrcT>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
   constexpr int T = Q / TS;           // texels per tile side
   constexpr int LOGQ = __builtin_ctz(Q);
+  constexpr int LOGTS = __builtin_ctz(TS);
+  constexpr int STRIDE = image_stride(Q);
+  constexpr int IMG = Q * STRIDE;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  __shared__ int cnt[kMaxChunks][kWaves][kOwners];
-  __shared__ int lbase[kOwners], lcount[kOwners];
-  __shared__ float red_s[kWaves], red_c[kWaves];
-  __shared__ unsigned face_mask;
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar registers
+  const int lane = threadIdx.x;
   const int64_t v = blockIdx.x;
   const int logn = p.logn;
   const int n = 1 << logn;
@@ -288,12 +279,10 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   const float eps = quotient_margin(logn);
   const bool comp = p.comp != 0;
 
-  constexpr int STRIDE = image_stride(Q);
-  constexpr int IMG = Q * STRIDE;
-  float* img = reinterpret_cast<float*>(dyn_lds) + wave * IMG;  // this wave's block image
-  int* lkey = reinterpret_cast<int*>(dyn_lds + kWaves * IMG * 4);
+  float* img = reinterpret_cast<float*>(dyn_lds);  // the block image
+  int* lkey = reinterpret_cast<int*>(dyn_lds + IMG * 4);
   float* lval = reinterpret_cast<float*>(lkey + p.listed);
-  double* gS = reinterpret_cast<double*>(dyn_lds + ((kWaves * IMG * 4 + 8 * p.listed + 7) & ~7));
+  double* gS = reinterpret_cast<double*>(dyn_lds + ((IMG * 4 + 8 * p.listed + 7) & ~7));
 
   // index row of this vertex: its own, or its cluster's support row
   const int32_t* idx_row = nullptr;
@@ -312,23 +301,21 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
 
   // faces touched by this vertex's transport row
   unsigned m = 0;
-  for (int e = tid; e < nnz; e += kThreads) {
+  for (int e = lane; e < nnz; e += kThreads) {
     const int idx = idx_row ? idx_row[e] : e;
     if (idx >= 0 && idx < 6 * (n << logn)) m |= 1u << (idx >> (2 * logn));
   }
-  if (tid == 0) face_mask = 0;
-  __syncthreads();
-  if (m) atomicOr(&face_mask, m);
-  __syncthreads();
-  const unsigned faces = __builtin_amdgcn_readfirstlane(face_mask);
+  unsigned faces = 0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) faces |= (__ballot((m >> f) & 1u) ? 1u : 0u) << f;
   const int nf = __popc(faces);
   const int ngroups = (nf + FG - 1) / FG;
 
   const bool owns_tile = lane < TS * TS;
-  constexpr int LOGTS = __builtin_ctz(TS);
   const int ty = lane >> LOGTS, tx = lane & (TS - 1);  // tile of this lane, and its texel in
                                                         // each TS x TS patch of the gather
   const uint64_t lanes_below = (uint64_t(1) << lane) - 1;
+  int nfine = 0, ncoarse = 0;
 
   for (int f = 0; f < p.nframes; ++f) {
     IRot R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr);
@@ -341,62 +328,29 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
       const int nfg = min(FG, nf - g0);
 
       if (f == 0 || ngroups > 1) {
-        // List the first `listed` entries by consumer (wave or coarse), in a
-        // fixed order: owner, then entry chunk, wave and lane.
-        const int nchunks = (listed + kThreads - 1) / kThreads;
-        for (int ch = 0; ch < nchunks; ++ch) {
-          const int e = ch * kThreads + tid;
-          int key = 0, owner = -1;
-          if (e < listed) owner = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
-#pragma unroll
-          for (int o = 0; o < kOwners; ++o) {
-            const uint64_t b = __ballot(owner == o);
-            if (lane == 0) cnt[ch][wave][o] = __popcll(b);
-          }
-        }
-        __syncthreads();
-        if (tid < kOwners) {
-          // running start of each (chunk, wave) run of owner tid, then totals
-          int run = 0;
-          for (int ch = 0; ch < nchunks; ++ch)
-            for (int w = 0; w < kWaves; ++w) {
-              const int c = cnt[ch][w][tid];
-              cnt[ch][w][tid] = run;
-              run += c;
-            }
-          lcount[tid] = run;
-        }
-        wave_sync();
-        if (tid < kOwners) {
-          int b = 0;
-          for (int o = 0; o < tid; ++o) b += lcount[o];
-          lbase[tid] = b;
-        }
-        __syncthreads();
-        for (int ch = 0; ch < nchunks; ++ch) {
-          const int e = ch * kThreads + tid;
-          int key = 0, owner = -1;
-          if (e < listed) owner = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
-          int rank = 0;
-#pragma unroll
-          for (int o = 0; o < kOwners; ++o) {
-            const uint64_t b = __ballot(owner == o);
-            if (owner == o) rank = __popcll(b & lanes_below);
-          }
-          if (owner >= 0) {
-            const int at = lbase[owner] + cnt[ch][wave][owner] + rank;
+        // List the first `listed` entries in entry order: block entries from
+        // the front, coarse entries from the back.
+        nfine = 0;
+        ncoarse = 0;
+        for (int c0 = 0; c0 < listed; c0 += kThreads) {
+          const int e = c0 + lane;
+          int key = 0, kind = -1;
+          if (e < listed) kind = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+          const uint64_t bf = __ballot(kind == 0), bc = __ballot(kind == 1);
+          if (kind >= 0) {
+            const int at = kind == 0 ? nfine + __popcll(bf & lanes_below)
+                                     : listed - 1 - (ncoarse + __popcll(bc & lanes_below));
             lkey[at] = key;
             lval[at] = transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e);
           }
+          nfine += __popcll(bf);
+          ncoarse += __popcll(bc);
         }
-        __syncthreads();
+        wave_sync();
       }
 
-      // Blocks of the group, round-robin over the waves; no barrier inside.
       const int nblk = nfg * G2;
-      const int my_base = __builtin_amdgcn_readfirstlane(lbase[wave]);
-      const int my_count = __builtin_amdgcn_readfirstlane(lcount[wave]);
-      for (int gi = wave; gi < nblk; gi += kWaves) {
+      for (int gi = 0; gi < nblk; ++gi) {
         const int r = gi / G2, blk = gi - r * G2;
         const int face = nth_face(faces, g0 + r);
         const FaceAxes ax = face_axes(R, face);
@@ -468,30 +422,29 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         if (lane == 0) gS[gi] = double(s) * (1.0 / Q);
         wave_sync();
         // listed entries of this block
-        for (int k = lane; k < my_count; k += 64) {
-          const int key = lkey[my_base + k];
+        for (int k = lane; k < nfine; k += kThreads) {
+          const int key = lkey[k];
           if (((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
-            acc_add(acc, lval[my_base + k],
-                    ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
+            acc_add(acc, lval[k], ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)),
+                    comp);
         }
         // entries past the list
-        for (int e = listed + lane; e < nnz; e += 64) {
+        for (int e = listed + lane; e < nnz; e += kThreads) {
           int key = 0;
-          const int owner = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
-          if (owner >= 0 && owner < kWaves && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
+          const int kind = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+          if (kind == 0 && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
             acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
                     ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
         }
         wave_sync();
       }
-      __syncthreads();
       // levels above the blocks, per face of the group (FP64, in place)
-      if (G > 1 && wave == 0) {
+      if (G > 1) {
         for (int r = 0; r < nfg; ++r) {
           double* gf = gS + r * G2;
           for (int Bg = 2; Bg <= G; Bg <<= 1) {
             const int hg = Bg / 2, nb = G / Bg;
-            for (int t = lane; t < nb * nb; t += 64) {
+            for (int t = lane; t < nb * nb; t += kThreads) {
               const int r0 = (t / nb) * Bg, c0 = (t % nb) * Bg;
               double S, H, V, D;
               tile_levels_d(gf[r0 * G + c0], gf[r0 * G + c0 + hg], gf[(r0 + hg) * G + c0],
@@ -505,23 +458,21 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
           }
         }
       }
-      __syncthreads();
       // coarse entries: blocks wider than Q and the faces' scaling coefficients
-      {
-        const int cb = lbase[kWaves], cn = lcount[kWaves];
-        for (int k = tid; k < cn; k += kThreads)
-          acc_add(acc, lval[cb + k], float(gS[lkey[cb + k]]), comp);
-        for (int e = listed + tid; e < nnz; e += kThreads) {
-          int key = 0;
-          if (classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key) == kWaves)
-            acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
-                    float(gS[key]), comp);
-        }
+      for (int k = lane; k < ncoarse; k += kThreads) {
+        const int at = listed - 1 - k;
+        acc_add(acc, lval[at], float(gS[lkey[at]]), comp);
       }
+      for (int e = listed + lane; e < nnz; e += kThreads) {
+        int key = 0;
+        if (classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key) == 1)
+          acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e), float(gS[key]),
+                  comp);
+      }
+      wave_sync();
     }
 
-    // workgroup reduction; its barrier also orders this frame's reads of the
-    // block sums and lists before the next frame's writes
+    // reduction across the wave
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
       Acc other;
@@ -533,23 +484,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         acc.s += other.s;
       }
     }
-    if (lane == 0) {
-      red_s[wave] = acc.s;
-      red_c[wave] = acc.c;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      Acc t = {red_s[0], red_c[0]};
-      for (int w = 1; w < kWaves; ++w) {
-        Acc o = {red_s[w], red_c[w]};
-        if (comp) {
-          t = acc_merge(t, o);
-        } else {
-          t.s += o.s;
-        }
-      }
-      p.out[int64_t(f) * p.nvert + v] = comp ? (t.s + t.c) : t.s;
-    }
+    if (lane == 0) p.out[int64_t(f) * p.nvert + v] = comp ? (acc.s + acc.c) : acc.s;
   }
 }
 
@@ -593,8 +528,7 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
 template <int Q, typename SrcT>
 int launch_q(const RelightParams& prm, int64_t nvert, hipStream_t s) {
   const int G = (1 << prm.logn) / Q;
-  const size_t lds = ((size_t(kWaves) * Q * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) &
-                      ~size_t(7)) +
+  const size_t lds = ((size_t(Q) * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) & ~size_t(7)) +
                      size_t(prm.group_faces) * G * G * 8;
   hipLaunchKernelGGL((relight_kernel<Q, SrcT>), dim3(unsigned(nvert)), dim3(kThreads), lds, s,
                      prm);
