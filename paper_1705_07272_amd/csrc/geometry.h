@@ -157,7 +157,8 @@ __device__ __forceinline__ int source_texel_exact(int x, int y, int z, int logn)
 template <int ES>
 __device__ __forceinline__ unsigned source_texel_scaled(int x, int y, int z, int logn, float eps) {
   const float fx = float(x), fy = float(y), fz = float(z);
-  const float hr = float(1 << logn) * __builtin_amdgcn_rcpf(fabsf(__builtin_amdgcn_cubema(fx, fy, fz)));
+  const float ma = __builtin_amdgcn_cubema(fx, fy, fz);
+  const float hr = float(1 << logn) * __builtin_amdgcn_rcpf(fabsf(ma));
   const float off = float(1 << (logn - 1)) + eps;
   const float qs = __builtin_fmaf(__builtin_amdgcn_cubesc(fx, fy, fz), hr, off);
   const float qt = __builtin_fmaf(__builtin_amdgcn_cubetc(fx, fy, fz), hr, off);

@@ -249,7 +249,8 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
   if (rank < 0 || rank >= FG) return -1;
   const int gi = rank * G * G + (s.pr >> LOGQ) * G + (s.pc >> LOGQ);
   if (s.logb <= LOGQ && (s.pr | s.pc) != 0) {
-    key = (s.logb << kLogbShift) | (gi << kOffBits) | ((s.pr & (Q - 1)) * STRIDE + (s.pc & (Q - 1)));
+    key = (s.logb << kLogbShift) | (gi << kOffBits) |
+          ((s.pr & (Q - 1)) * STRIDE + (s.pc & (Q - 1)));
     return 0;
   }
   key = gi;
@@ -349,94 +350,101 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         wave_sync();
       }
 
-      const int nblk = nfg * G2;
-      for (int gi = 0; gi < nblk; ++gi) {
-        const int r = gi / G2, blk = gi - r * G2;
+      for (int r = 0, gi = 0; r < nfg; ++r) {
         const int face = nth_face(faces, g0 + r);
         const FaceAxes ax = face_axes(R, face);
-        const int by = blk / G, bx = blk - by * G;
-        // Gather in TS x TS patches of adjacent texels (one load instruction
-        // covers a compact patch, which the L1 serves with few cache lines):
-        // lane (ty, tx) takes texel (TS a + ty, TS b + tx) of every patch
-        // (a, b) and stores it raw into the block image.
-        if (owns_tile) {
-          const int i0 = (by << LOGQ) + ty, j0 = (bx << LOGQ) + tx;
-          const int U0 = 2 * j0 + 1 - n, V0 = 2 * i0 + 1 - n;
-          int rx = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
-          int ry = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
-          int rz = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
-          // all T^2 loads are issued before the first store, so that they
-          // are in flight together
-          float val[T][T];
+        // this lane's direction at texel (ty, tx) of block (0, 0); a block
+        // (by, bx) adds the uniform 2 Q (bx R e_U + by R e_V)
+        const int U0 = 2 * tx + 1 - n, V0 = 2 * ty + 1 - n;
+        const int lx = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
+        const int ly = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
+        const int lz = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
+        for (int by = 0; by < G; ++by) {
+          for (int bx = 0; bx < G; ++bx, ++gi) {
+            // Gather in TS x TS patches of adjacent texels (one load instruction
+            // covers a compact patch, which the L1 serves with few cache lines):
+            // lane (ty, tx) takes texel (TS a + ty, TS b + tx) of every patch
+            // (a, b) and stores it raw into the block image.
+            if (owns_tile) {
+              int rx = wrap_mad(ax.mU.x, 2 * Q * bx, wrap_mad(ax.mV.x, 2 * Q * by, lx));
+              int ry = wrap_mad(ax.mU.y, 2 * Q * bx, wrap_mad(ax.mV.y, 2 * Q * by, ly));
+              int rz = wrap_mad(ax.mU.z, 2 * Q * bx, wrap_mad(ax.mV.z, 2 * Q * by, lz));
+              // all T^2 loads are issued before the first store, so that they
+              // are in flight together
+              float val[T][T];
 #pragma unroll
-          for (int a = 0; a < T; ++a) {
-            int dx = rx, dy = ry, dz = rz;
+              for (int a = 0; a < T; ++a) {
+                int dx = rx, dy = ry, dz = rz;
 #pragma unroll
-            for (int b = 0; b < T; ++b) {
-              val[a][b] = load_src<SrcT>(
-                  src, source_texel_scaled<sizeof(SrcT) == 4 ? 2 : 1>(dx, dy, dz, logn, eps));
-              dx = wrap_mad(ax.mU.x, 2 * TS, dx);
-              dy = wrap_mad(ax.mU.y, 2 * TS, dy);
-              dz = wrap_mad(ax.mU.z, 2 * TS, dz);
+                for (int b = 0; b < T; ++b) {
+                  val[a][b] = load_src<SrcT>(
+                      src, source_texel_scaled<sizeof(SrcT) == 4 ? 2 : 1>(dx, dy, dz, logn, eps));
+                  dx = wrap_mad(ax.mU.x, 2 * TS, dx);
+                  dy = wrap_mad(ax.mU.y, 2 * TS, dy);
+                  dz = wrap_mad(ax.mU.z, 2 * TS, dz);
+                }
+                rx = wrap_mad(ax.mV.x, 2 * TS, rx);
+                ry = wrap_mad(ax.mV.y, 2 * TS, ry);
+                rz = wrap_mad(ax.mV.z, 2 * TS, rz);
+              }
+#pragma unroll
+              for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
             }
-            rx = wrap_mad(ax.mV.x, 2 * TS, rx);
-            ry = wrap_mad(ax.mV.y, 2 * TS, ry);
-            rz = wrap_mad(ax.mV.z, 2 * TS, rz);
+            wave_sync();
+            float s = 0.0f;  // unscaled sum of this lane's tile, then of its block
+            if (owns_tile) {
+              // the lane's T x T tile: levels up to side T in registers, in place
+              float g[T][T];
+#pragma unroll
+              for (int rr = 0; rr < T; ++rr)
+#pragma unroll
+                for (int cc = 0; cc < T; ++cc)
+                  g[rr][cc] = img[(ty * T + rr) * STRIDE + tx * T + cc];
+              tile_levels<T>(g);
+#pragma unroll
+              for (int rr = 0; rr < T; ++rr)
+#pragma unroll
+                for (int cc = 0; cc < T; ++cc)
+                  img[(ty * T + rr) * STRIDE + tx * T + cc] = g[rr][cc];
+              s = g[0][0];
+            }
+            // levels above the tile, unscaled: the four tiles of a block of side
+            // 2 ht tiles are lanes l, l ^ ht, l ^ ht TS and l ^ (ht TS + ht)
+#pragma unroll
+            for (int ht = 1; ht < TS; ht <<= 1) {
+              const float b = __shfl_xor(s, ht, 64);
+              const float c = __shfl_xor(s, ht * TS, 64);
+              const float d = __shfl_xor(s, ht * TS + ht, 64);
+              if (owns_tile && ((tx | ty) & (2 * ht - 1)) == 0) {
+                img[(ty * T) * STRIDE + (tx + ht) * T] = (s - b) + (c - d);
+                img[((ty + ht) * T) * STRIDE + tx * T] = (s + b) - (c + d);
+                img[((ty + ht) * T) * STRIDE + (tx + ht) * T] = (s - b) - (c - d);
+                s = (s + b) + (c + d);
+              }
+            }
+            // the block's orthonormal scaling coefficient, for the levels above
+            if (lane == 0) gS[gi] = double(s) * (1.0 / Q);
+            wave_sync();
+            // listed entries of this block
+            for (int k = lane; k < nfine; k += kThreads) {
+              const int key = lkey[k];
+              if (((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
+                acc_add(acc, lval[k],
+                        ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
+            }
+            // entries past the list
+            for (int e = listed + lane; e < nnz; e += kThreads) {
+              int key = 0;
+              const int kind = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+              if (kind == 0 && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
+                acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
+                        ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
+            }
+            wave_sync();
           }
-#pragma unroll
-          for (int a = 0; a < T; ++a)
-#pragma unroll
-            for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
         }
-        wave_sync();
-        float s = 0.0f;  // unscaled sum of this lane's tile, then of its block
-        if (owns_tile) {
-          // the lane's T x T tile: levels up to side T in registers, in place
-          float g[T][T];
-#pragma unroll
-          for (int rr = 0; rr < T; ++rr)
-#pragma unroll
-            for (int cc = 0; cc < T; ++cc) g[rr][cc] = img[(ty * T + rr) * STRIDE + tx * T + cc];
-          tile_levels<T>(g);
-#pragma unroll
-          for (int rr = 0; rr < T; ++rr)
-#pragma unroll
-            for (int cc = 0; cc < T; ++cc) img[(ty * T + rr) * STRIDE + tx * T + cc] = g[rr][cc];
-          s = g[0][0];
-        }
-        // levels above the tile, unscaled: the four tiles of a block of side
-        // 2 ht tiles are lanes l, l ^ ht, l ^ ht TS and l ^ (ht TS + ht)
-#pragma unroll
-        for (int ht = 1; ht < TS; ht <<= 1) {
-          const float b = __shfl_xor(s, ht, 64);
-          const float c = __shfl_xor(s, ht * TS, 64);
-          const float d = __shfl_xor(s, ht * TS + ht, 64);
-          if (owns_tile && ((tx | ty) & (2 * ht - 1)) == 0) {
-            img[(ty * T) * STRIDE + (tx + ht) * T] = (s - b) + (c - d);
-            img[((ty + ht) * T) * STRIDE + tx * T] = (s + b) - (c + d);
-            img[((ty + ht) * T) * STRIDE + (tx + ht) * T] = (s - b) - (c - d);
-            s = (s + b) + (c + d);
-          }
-        }
-        // the block's orthonormal scaling coefficient, for the levels above
-        if (lane == 0) gS[gi] = double(s) * (1.0 / Q);
-        wave_sync();
-        // listed entries of this block
-        for (int k = lane; k < nfine; k += kThreads) {
-          const int key = lkey[k];
-          if (((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
-            acc_add(acc, lval[k], ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)),
-                    comp);
-        }
-        // entries past the list
-        for (int e = listed + lane; e < nnz; e += kThreads) {
-          int key = 0;
-          const int kind = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
-          if (kind == 0 && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
-            acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
-                    ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
-        }
-        wave_sync();
       }
       // levels above the blocks, per face of the group (FP64, in place)
       if (G > 1) {
