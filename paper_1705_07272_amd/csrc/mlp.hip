@@ -3,13 +3,16 @@
 // backward passes, MSE loss, bias-gradient column sums and Adam.
 //
 // GEMM: C[M][N] = sum_k A(m, k) B(k, n), A and B in bfloat16, FP32
-// accumulation on the matrix cores (v_mfma_f32_32x32x8_bf16, wave64).  A is
+// accumulation on the matrix cores (v_mfma_f32_32x32x16_bf16, wave64).  A is
 // stored [M][K] (row-major) or, transposed, [K][M]; B is stored [K][N] or,
-// transposed, [N][K].  A 256-thread workgroup computes a 64 x 64 tile of C:
-// each k-step stages a 64 x 32 slice of A and a 32 x 64 slice of B in LDS in
-// k-contiguous order, and each of the four waves runs four 32x32x8 MFMAs on
-// its 32 x 32 quadrant.  Rows, columns and k beyond the matrix read as zero
-// and are not stored, so any M, N, K work.
+// transposed, [N][K]; the contiguous dimension of each is a multiple of 8.
+// A 256-thread workgroup computes a (64 TM) x (64 TM) tile of C, each of its
+// four waves a TM x TM grid of 32 x 32 MFMA tiles.  Each 32-deep k-slice of A
+// and B is loaded with 16-byte vector loads (the next slice is in flight
+// while the matrix cores consume the current one) and staged in LDS in
+// k-contiguous rows (row stride 40 bf16), from which every lane reads its 8
+// k-consecutive operands with one 16-byte LDS read.  Rows, columns and k
+// beyond the matrix read as zero and are not stored.
 #include <hip/hip_fp16.h>
 
 #include "rrt_internal.h"
@@ -17,12 +20,13 @@
 namespace rrt {
 namespace {
 
-constexpr int kBM = 64, kBN = 64, kBK = 32;
-constexpr int kLdsStride = kBK + 8;  // bf16 elements per LDS row (padding vs bank conflicts)
+constexpr int kBK = 32;
+constexpr int kLdsStride = kBK + 8;  // bf16 elements per LDS row (16-byte rows, staggered banks)
 constexpr float kSqrt2OverPi = 0.7978845608028654f;
 constexpr float kGeluC = 0.044715f;
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) {
@@ -32,13 +36,19 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
-__device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.0f + tanhf(kSqrt2OverPi * (z + kGeluC * z * z * z)));
+// GELU with the tanh approximation, written with the identity
+// (1 + tanh u) / 2 = 1 / (1 + exp(-2u)): gelu(z) = z sigma(2u),
+// u = sqrt(2/pi) (z + 0.044715 z^3); its derivative is
+// sigma + 2 z sigma (1 - sigma) du/dz.
+__device__ __forceinline__ float gelu_sigma(float z) {
+  const float u = kSqrt2OverPi * (z + kGeluC * z * z * z);
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
 }
+__device__ __forceinline__ float gelu_f(float z) { return z * gelu_sigma(z); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  const float t = tanhf(kSqrt2OverPi * (z + kGeluC * z * z * z));
+  const float sg = gelu_sigma(z);
   const float du = kSqrt2OverPi * (1.0f + 3.0f * kGeluC * z * z);
-  return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * du;
+  return sg + 2.0f * z * sg * (1.0f - sg) * du;
 }
 
 enum Epilogue {
@@ -58,83 +68,116 @@ struct GemmArgs {
   uint16_t* out_bf16;  // [M][N]
 };
 
-template <bool AT, bool BT, int EPI>
-__global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
-  __shared__ uint16_t As[kBM * kLdsStride];
-  __shared__ uint16_t Bs[kBN * kLdsStride];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  float16_t acc = {};
+// 8 consecutive bf16 of a row-major [rows][cols] matrix from (r, c), or zeros
+// outside it (c and cols are multiples of 8).
+__device__ __forceinline__ u32x4_t load8(const uint16_t* base, int rows, int cols, int r, int c) {
+  u32x4_t v = {0u, 0u, 0u, 0u};
+  if (r < rows && c < cols) v = *reinterpret_cast<const u32x4_t*>(base + int64_t(r) * cols + c);
+  return v;
+}
 
+// One operand's k-slice: R rows x kBK k, from a k-contiguous ([rows][K]) or
+// row-contiguous ([K][rows]) matrix, 16 bytes per vector, R / 64 per thread.
+template <int R, bool KCONTIG>
+struct Slice {
+  static constexpr int kPer = R * kBK / 8 / 256;
+  u32x4_t v[kPer];
+  __device__ __forceinline__ void load(const uint16_t* base, int rows, int K, int r0, int k0) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = i * 256 + int(threadIdx.x);
+      if (KCONTIG) {
+        v[i] = load8(base, rows, K, r0 + (e >> 2), k0 + (e & 3) * 8);
+      } else {
+        v[i] = load8(base, K, rows, k0 + e / (R / 8), r0 + (e % (R / 8)) * 8);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t* lds) const {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = i * 256 + int(threadIdx.x);
+      if (KCONTIG) {
+        *reinterpret_cast<u32x4_t*>(lds + (e >> 2) * kLdsStride + (e & 3) * 8) = v[i];
+      } else {
+        const int k = e / (R / 8), r = (e % (R / 8)) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          lds[(r + j) * kLdsStride + k] = uint16_t(v[i][j / 2] >> (16 * (j & 1)));
+      }
+    }
+  }
+};
+
+template <bool AT, bool BT, int EPI, int TM>
+__global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
+  constexpr int BM = 64 * TM, BN = 64 * TM;
+  __shared__ __align__(16) uint16_t As[BM * kLdsStride];
+  __shared__ __align__(16) uint16_t Bs[BN * kLdsStride];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 32 * TM, wn = (wave & 1) * 32 * TM;
+  float16_t acc[TM][TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[i][j] = float16_t{};
+
+  Slice<BM, !AT> sa;
+  Slice<BN, BT> sb;
+  sa.load(g.A, g.M, g.K, m0, 0);
+  sb.load(g.B, g.N, g.K, n0, 0);
   for (int k0 = 0; k0 < g.K; k0 += kBK) {
-    // stage A(m0.., k0..) as As[m][k]
-#pragma unroll
-    for (int it = 0; it < (kBM * kBK) / 256; ++it) {
-      const int e = it * 256 + tid;
-      int m, k;
-      if (!AT) {        // [M][K]: k fastest
-        m = e / kBK;
-        k = e % kBK;
-      } else {          // [K][M]: m fastest
-        k = e / kBM;
-        m = e % kBM;
-      }
-      const int gm = m0 + m, gk = k0 + k;
-      uint16_t val = 0;
-      if (gm < g.M && gk < g.K) val = AT ? g.A[int64_t(gk) * g.M + gm] : g.A[int64_t(gm) * g.K + gk];
-      As[m * kLdsStride + k] = val;
-    }
-    // stage B(k0.., n0..) as Bs[n][k]
-#pragma unroll
-    for (int it = 0; it < (kBN * kBK) / 256; ++it) {
-      const int e = it * 256 + tid;
-      int n, k;
-      if (BT) {         // [N][K]: k fastest
-        n = e / kBK;
-        k = e % kBK;
-      } else {          // [K][N]: n fastest
-        k = e / kBN;
-        n = e % kBN;
-      }
-      const int gn = n0 + n, gk = k0 + k;
-      uint16_t val = 0;
-      if (gn < g.N && gk < g.K) val = BT ? g.B[int64_t(gn) * g.K + gk] : g.B[int64_t(gk) * g.N + gn];
-      Bs[n * kLdsStride + k] = val;
-    }
+    sa.store(As);
+    sb.store(Bs);
     __syncthreads();
+    if (k0 + kBK < g.K) {
+      sa.load(g.A, g.M, g.K, m0, k0 + kBK);
+      sb.load(g.B, g.N, g.K, n0, k0 + kBK);
+    }
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 8) {
-      const int kq = kk + 4 * (lane >> 5);
-      const uint16_t* pa = &As[(wm + (lane & 31)) * kLdsStride + kq];
-      const uint16_t* pb = &Bs[(wn + (lane & 31)) * kLdsStride + kq];
-      short4_t a, b;
-      a[0] = short(pa[0]); a[1] = short(pa[1]); a[2] = short(pa[2]); a[3] = short(pa[3]);
-      b[0] = short(pb[0]); b[1] = short(pb[1]); b[2] = short(pb[2]); b[3] = short(pb[3]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int kk = 0; kk < kBK; kk += 16) {
+      // lane l: operand row l % 32, k = kk + 8 (l / 32) .. + 7
+      const int ko = kk + 8 * (lane >> 5);
+      bf16x8_t a[TM], b[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = *reinterpret_cast<const bf16x8_t*>(&As[(wm + 32 * i + (lane & 31)) * kLdsStride + ko]);
+#pragma unroll
+      for (int j = 0; j < TM; ++j)
+        b[j] = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn + 32 * j + (lane & 31)) * kLdsStride + ko]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
-  // D[m][n]: register j of lane l holds row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32
+  // D[m][n]: register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int m = m0 + wm + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-    const int n = n0 + wn + (lane & 31);
-    if (m >= g.M || n >= g.N) continue;
-    const int64_t at = int64_t(m) * g.N + n;
-    float x = acc[j];
-    if (EPI == kEpiHidden) {
-      x += g.bias[n];
-      g.out_f32[at] = x;
-      g.out_bf16[at] = bf16_bits(gelu_f(x));
-    } else if (EPI == kEpiOutput) {
-      g.out_f32[at] = x + g.bias[n];
-    } else if (EPI == kEpiGeluGrad) {
-      g.out_bf16[at] = bf16_bits(x * gelu_grad_f(g.zprev[at]));
-    } else {
-      g.out_f32[at] = x;
-    }
-  }
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int n = n0 + wn + 32 * j + (lane & 31);
+        if (m >= g.M || n >= g.N) continue;
+        const int64_t at = int64_t(m) * g.N + n;
+        float x = acc[i][j][r];
+        if (EPI == kEpiHidden) {
+          x += g.bias[n];
+          g.out_f32[at] = x;
+          g.out_bf16[at] = bf16_bits(gelu_f(x));
+        } else if (EPI == kEpiOutput) {
+          g.out_f32[at] = x + g.bias[n];
+        } else if (EPI == kEpiGeluGrad) {
+          g.out_bf16[at] = bf16_bits(x * gelu_grad_f(g.zprev[at]));
+        } else {
+          g.out_f32[at] = x;
+        }
+      }
 }
 
 // gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7), zero-padded to 128.
@@ -216,10 +259,19 @@ __global__ void adam_kernel(float* __restrict__ p, uint16_t* __restrict__ p_bf16
   if (p_bf16) p_bf16[t] = bf16_bits(pt);
 }
 
+// 128 x 128 tiles when they still give every CU a workgroup, else 64 x 64.
 template <bool AT, bool BT, int EPI>
 int gemm(const GemmArgs& a, hipStream_t s) {
-  const dim3 grid(unsigned((a.N + kBN - 1) / kBN), unsigned((a.M + kBM - 1) / kBM));
-  hipLaunchKernelGGL((gemm_bf16<AT, BT, EPI>), grid, dim3(256), 0, s, a);
+  // the contiguous dimension of each stored operand must allow 16-byte loads
+  if ((AT ? a.M : a.K) % 8 || (BT ? a.K : a.N) % 8) return RRT_ERR_UNSUPPORTED;
+  const int64_t big = int64_t((a.N + 127) / 128) * ((a.M + 127) / 128);
+  if (big >= 512) {
+    const dim3 grid(unsigned((a.N + 127) / 128), unsigned((a.M + 127) / 128));
+    hipLaunchKernelGGL((gemm_bf16<AT, BT, EPI, 2>), grid, dim3(256), 0, s, a);
+  } else {
+    const dim3 grid(unsigned((a.N + 63) / 64), unsigned((a.M + 63) / 64));
+    hipLaunchKernelGGL((gemm_bf16<AT, BT, EPI, 1>), grid, dim3(256), 0, s, a);
+  }
   return check_launch("gemm_bf16");
 }
 
