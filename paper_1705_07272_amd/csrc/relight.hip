@@ -427,12 +427,16 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             // the block's orthonormal scaling coefficient, for the levels above
             if (lane == 0) gS[gi] = double(s) * (1.0 / Q);
             wave_sync();
-            // listed entries of this block
-            for (int k = lane; k < nfine; k += kThreads) {
-              const int key = lkey[k];
-              if (((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
-                acc_add(acc, lval[k],
-                        ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
+            // listed entries of this block: four keys per lane and LDS read
+            for (int k0 = 4 * lane; k0 < nfine; k0 += 4 * kThreads) {
+              const int4 keys = *reinterpret_cast<const int4*>(&lkey[k0]);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int key = q == 0 ? keys.x : (q == 1 ? keys.y : (q == 2 ? keys.z : keys.w));
+                if (k0 + q < nfine && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
+                  acc_add(acc, lval[k0 + q],
+                          ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
+              }
             }
             // entries past the list
             for (int e = listed + lane; e < nnz; e += kThreads) {
