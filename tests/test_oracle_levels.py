@@ -1,0 +1,112 @@
+"""Pins of the coarse-level start (oracle/levels.py) against facts fixed by
+the orthonormal Haar pyramid and the cube group, independent of the code
+under test: the index remap is a bijection of the coarse corner, the coarse
+corner of the pyramid equals the pyramid of the block-sum map, k = 0 is the
+full method, the identity rotation reduces to a plain inner product, a
+cube-group rotation commutes with the coarsening, constant lighting has its
+closed form."""
+import numpy as np
+import pytest
+
+from oracle.haar import haar_forward
+from oracle.levels import coarse_index, relight_from_level
+from oracle.relight import relight
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _block_sum_over_B(P, B):
+    F, n, _ = P.shape
+    return P.reshape(F, n // B, B, n // B, B).sum(axis=(2, 4)) / B
+
+
+def test_coarse_index_bijection_and_hand_values():
+    n, k = 8, 1
+    ci = coarse_index(np.arange(6 * n * n), n, k)
+    kept = ci[ci >= 0]
+    assert np.array_equal(np.sort(kept), np.arange(6 * 4 * 4))
+    assert (ci < 0).sum() == 6 * (64 - 16)
+    # face 2, row 1, column 3 -> 2*16 + 1*4 + 3; face 0, row 4 -> finer level
+    assert coarse_index([2 * 64 + 1 * 8 + 3], n, k)[0] == 39
+    assert coarse_index([0 * 64 + 4 * 8 + 0], n, k)[0] == -1
+    assert coarse_index([-5, 6 * 64], n, k).tolist() == [-1, -1]
+
+
+@pytest.mark.parametrize("n,k", [(8, 1), (16, 2), (32, 3)])
+def test_coarse_corner_is_pyramid_of_block_sums(n, k):
+    rng = np.random.default_rng(n + k)
+    P = rng.normal(size=(6, n, n))
+    B = 1 << k
+    nc = n // B
+    full = haar_forward(P)
+    coarse = haar_forward(_block_sum_over_B(P, B))
+    np.testing.assert_allclose(full[:, :nc, :nc], coarse, rtol=1e-12, atol=1e-12)
+
+
+def _scene(n, V, nnz, seed):
+    rng = np.random.default_rng(seed)
+    K = 6 * n * n // 3
+    li = np.sort(rng.choice(6 * n * n, K, replace=False)).astype(np.int32)
+    lv = rng.normal(size=K)
+    ti = np.stack([np.sort(rng.choice(6 * n * n, nnz, replace=False)) for _ in range(V)]).astype(np.int32)
+    tv = rng.normal(size=(V, nnz))
+    return li, lv, ti, tv
+
+
+def test_level_zero_is_the_full_method():
+    n = 8
+    li, lv, ti, tv = _scene(n, 3, 40, 1)
+    rng = np.random.default_rng(2)
+    q = rng.normal(size=(3, 4))
+    from scenes.scene import quaternion_rotations
+    R = quaternion_rotations(q).astype(np.float32)
+    np.testing.assert_array_equal(relight_from_level(li, lv, n, R, None, ti, tv, 0),
+                                  relight(li, lv, n, R, None, ti, tv))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_identity_rotation_is_a_plain_inner_product(k):
+    n = 16
+    li, lv, ti, tv = _scene(n, 4, 200, 3)
+    R = np.tile(np.eye(3, dtype=np.float32), (4, 1, 1))
+    got = relight_from_level(li, lv, n, R, None, ti, tv, k)
+    L = np.zeros(6 * n * n)
+    L[li] = lv
+    for v in range(4):
+        keep = coarse_index(ti[v], n, k) >= 0
+        want = np.dot(L[ti[v][keep]], tv[v][keep])
+        assert abs(got[0, v] - want) <= 1e-12 * (1 + abs(want))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_cube_rotation_commutes_with_coarsening(k):
+    """A quarter turn maps blocks onto blocks: rotating at n' equals the
+    full-resolution result restricted to the coarse coefficients."""
+    n = 16
+    li, lv, ti, tv = _scene(n, 3, 300, 4)
+    rots = np.array([[[0, 0, 1], [0, 1, 0], [-1, 0, 0]],
+                     [[1, 0, 0], [0, 0, -1], [0, 1, 0]],
+                     [[0, -1, 0], [1, 0, 0], [0, 0, 1]]], dtype=np.float32)
+    got = relight_from_level(li, lv, n, rots, None, ti, tv, k)
+    for v in range(3):
+        keep = coarse_index(ti[v], n, k) >= 0
+        want = relight(li, lv, n, rots[v:v + 1], None, ti[v:v + 1, keep], tv[v:v + 1, keep])
+        assert abs(got[0, v] - want[0, 0]) <= 1e-11 * (1 + abs(want[0, 0]))
+
+
+def test_constant_lighting_closed_form():
+    n, k, c = 16, 2, 1.75
+    li = np.arange(6 * n * n, dtype=np.int32)
+    lv = haar_forward(np.full((6, n, n), c)).ravel()
+    rng = np.random.default_rng(5)
+    ti = np.stack([np.sort(rng.choice(6 * n * n, 100, replace=False)) for _ in range(2)])
+    ti[:, 0] = 0                      # face 0 scaling coefficient always present
+    ti = np.sort(ti, axis=1).astype(np.int32)
+    tv = rng.normal(size=(2, 100))
+    from scenes.scene import quaternion_rotations
+    R = quaternion_rotations(rng.normal(size=(2, 4))).astype(np.float32)
+    got = relight_from_level(li, lv, n, R, None, ti, tv, k)
+    for v in range(2):
+        dc = [f * n * n for f in range(6)]
+        want = sum(n * c * tv[v][ti[v] == d].sum() for d in dc)
+        assert abs(got[0, v] - want) <= 1e-10 * (1 + abs(want))
