@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--form", choices=["f32", "bf16", "s16", "e4m3", "mlp"], default="f32",
                     help="transport storage; the reduced forms also store the lighting in "
                          "binary16 and accumulate with compensation")
+    ap.add_argument("--start-level", type=int, default=0,
+                    help="rotate from this many levels below the finest one (Sec. V.C remark; "
+                         "an approximation of the exact method, 0 = exact)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--mlp-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -288,6 +291,11 @@ def main():
     inp = device_inputs(w, args.form)
     print("inputs ready", file=sys.stderr, flush=True)
     n, K, V = w.n, w.k_light, w.nverts
+    L = args.start_level
+    n_rot = n >> L                     # resolution the rotation runs at
+    if L:
+        # stored transport rows re-indexed once (a storage transformation)
+        inp["idx"] = rrt.coarsen_indices(inp["idx"], n, L)
     F = 1 if inp["frot"] is None else inp["frot"].shape[0]
     ws = torch.empty(2 * 6 * n * n * 4 + 512, dtype=torch.uint8, device="cuda")
     out = torch.empty((F, V), dtype=torch.float32, device="cuda")
@@ -297,7 +305,9 @@ def main():
         coef = rrt.haar_forward(inp["pix"])                               # a1
         li, lv = rrt.topk(coef.view(1, -1), K)                            # a2
         lv = rrt.convert(lv, "f16") if light_f16 else lv
-        prep = rrt.prepare_lighting(n, li[0], lv[0], workspace=ws)        # a3
+        if L:
+            li = rrt.coarsen_indices(li, n, L)
+        prep = rrt.prepare_lighting(n_rot, li[0], lv[0], workspace=ws)    # a3
         if ev is not None:
             ev[0].record()
         rrt.relight_prepared(prep, inp["rot"], inp["idx"], inp["val"], frame_rot=inp["frot"],
@@ -322,10 +332,11 @@ def main():
     ms_kernel = sum(a.elapsed_time(b) for a, b in evs) / args.steps
 
     # algorithmic work of one relight launch
-    faces = torch.zeros((V, 6), dtype=torch.float32, device="cuda")
-    faces.scatter_(1, (inp["idx"].long() // (n * n)).clamp(0, 5), 1.0)
-    face_count = int((faces > 0).sum().item())
-    texels = face_count * n * n * F
+    faces = torch.zeros((V, 7), dtype=torch.float32, device="cuda")
+    fid = inp["idx"].long() // (n_rot * n_rot)
+    faces.scatter_(1, torch.where(inp["idx"] >= 0, fid, torch.full_like(fid, 6)), 1.0)
+    face_count = int((faces[:, :6] > 0).sum().item())
+    texels = face_count * n_rot * n_rot * F
     val_bytes = inp["val"].element_size()
     hbm_bytes = (V * w.nnz * (4 + val_bytes) + V * 36 + F * V * 4
                  + (0 if inp["scale"] is None else inp["scale"].numel() * 4)
@@ -357,6 +368,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "cube_face": n, "light_coeffs": K, "vertices": V,
                    "frames": F, "transport_nnz": w.nnz, "form": args.form},
+        **({"start_level": {"levels": L, "rotated_face": n_rot,
+                            "note": "approximation; its error against the exact FP64 oracle "
+                                    "is measured by tests/test_oracle_levels.py"}} if L else {}),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
                      "traffic": traffic, "kernel": "relight_kernel",

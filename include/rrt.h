@@ -200,6 +200,23 @@ int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst,
                 float* block_scale, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Rotation started below the finest level (Sec. V.C, remark after the
+ * algorithm: starting `levels` levels coarser divides the rotation work by
+ * 4^levels).
+ *   out[i] = index at resolution n >> levels of coefficient idx[i] at
+ *   resolution n (same face, same Mallat row and column), or -1 when the
+ *   coefficient belongs to one of the `levels` finest levels or idx[i] is
+ *   outside [0, 6 n^2).  Relighting at n >> levels with the remapped
+ *   lighting and transport indices (-1 entries are ignored) rotates the
+ *   coarser levels only: the map of 2^levels x 2^levels block sums divided
+ *   by 2^levels has exactly those coefficients.
+ *   idx, out: [count] int32 device arrays (may be the same array);
+ *   n a power of two in [4, 1024], 1 <= levels and n >> levels >= 2.
+ * --------------------------------------------------------------------- */
+int rrt_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
+                        void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned transport decoder (not part of the paper): an MLP maps a vertex's
  * position and normal to its transport values on a per-cluster support.
  *   encode:  gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7) of the 6

@@ -13,7 +13,7 @@ from . import _abi
 from ._abi import (RRT_BF16, RRT_BLOCK, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
                    RRT_S16, Light, RrtError, Rotations, Transport, check, lib)
 
-__all__ = ["haar_forward", "haar_inverse", "topk", "haar_phase_shift", "relight", "mlp_encode",
+__all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight", "mlp_encode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
@@ -79,6 +79,15 @@ def topk(x, k):
     check(lib.rrt_topk(_dev(x, "x", torch.float32), rows, length, k, _dev(idx, "idx"),
                        _dev(val, "val"), _dev(ws, "ws"), nbytes.value, _stream()))
     return idx, val
+
+
+def coarsen_indices(idx, n, levels):
+    """Flat coefficient indices at resolution n -> the same coefficients'
+    indices at n >> levels, -1 for the `levels` finest levels."""
+    out = torch.empty_like(idx)
+    check(lib.rrt_coarsen_indices(_dev(idx, "idx", torch.int32), idx.numel(), n, levels,
+                                  _dev(out, "out"), _stream()))
+    return out
 
 
 def haar_phase_shift(coef, rot):

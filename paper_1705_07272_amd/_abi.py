@@ -62,6 +62,7 @@ SIGNATURES = {
     "rrt_haar_forward": (c_int, [c_void_p, c_void_p, c_int, c_int64, c_void_p]),
     "rrt_haar_inverse": (c_int, [c_void_p, c_void_p, c_int, c_int64, c_void_p]),
     "rrt_topk_workspace": (c_int, [c_int64, c_int64, c_int, P(c_size_t)]),
+    "rrt_coarsen_indices": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p]),
     "rrt_topk": (c_int, [c_void_p, c_int64, c_int64, c_int, c_void_p, c_void_p, c_void_p,
                          c_size_t, c_void_p]),
     "rrt_haar_phase_shift_workspace": (c_int, [c_int, c_int, P(c_size_t)]),

@@ -152,6 +152,17 @@ int rrt_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, flo
   return launch_topk(x, rows, len, k, idx, val, ws, static_cast<hipStream_t>(stream));
 }
 
+int rrt_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
+                        void* stream) {
+  if (!valid_n(n, 4)) return fail(RRT_ERR_INVALID, "coarsen: n=%d not a power of two in [4,1024]", n);
+  if (levels < 1 || (n >> levels) < 2)
+    return fail(RRT_ERR_INVALID, "coarsen: levels=%d needs 1 <= levels and n >> levels >= 2", levels);
+  if (count < 0 || count >= (int64_t(1) << 40)) return fail(RRT_ERR_INVALID, "coarsen: bad count");
+  if (count == 0) return RRT_OK;
+  if (!idx || !out) return fail(RRT_ERR_INVALID, "coarsen: null pointer");
+  return launch_coarsen_indices(idx, count, n, levels, out, static_cast<hipStream_t>(stream));
+}
+
 int rrt_haar_phase_shift_workspace(int n, int nrot, size_t* bytes) {
   if (!bytes) return fail(RRT_ERR_INVALID, "phase_shift_workspace: null bytes");
   if (!valid_n(n, 2) || nrot < 0) return fail(RRT_ERR_INVALID, "phase_shift_workspace: bad sizes");

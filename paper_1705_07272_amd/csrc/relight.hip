@@ -515,6 +515,26 @@ __global__ void scatter_light(const int32_t* __restrict__ idx, const void* __res
                   : static_cast<const float*>(val)[i];
 }
 
+// Index of coefficient idx at resolution n in the map n >> levels, or -1 for
+// the `levels` finest levels (Mallat layout: the coarse levels are the
+// top-left corner of each face).
+__global__ void coarsen_indices(const int32_t* __restrict__ idx, int64_t count, int logn,
+                                int levels, int32_t* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int n = 1 << logn;
+  const int per_face = n << logn;
+  const int v = idx[i];
+  int r = -1;
+  if (v >= 0 && v < 6 * per_face) {
+    const int face = v >> (2 * logn), pos = v & (per_face - 1);
+    const int row = pos >> logn, col = pos & (n - 1);
+    const int lc = logn - levels;
+    if ((row >> lc) == 0 && (col >> lc) == 0) r = (face << (2 * lc)) + (row << lc) + col;
+  }
+  out[i] = r;
+}
+
 // dst[r][q] = src[pi_r(q)] for every texel q of the local map, r < nrot.
 __global__ void rotate_pixels(const float* __restrict__ src, const float* __restrict__ rot,
                               int logn, float* __restrict__ dst) {
@@ -594,6 +614,14 @@ int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, 
   hipLaunchKernelGGL(scatter_light, dim3(unsigned((k + 255) / 256)), dim3(256), 0, s, idx, val,
                      dtype == RRT_F16 ? 1 : 0, k, int(total), dense);
   return check_launch("scatter_light");
+}
+
+int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
+                           hipStream_t s) {
+  if (count == 0) return RRT_OK;
+  hipLaunchKernelGGL(coarsen_indices, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, idx,
+                     count, ilog2(n), levels, out);
+  return check_launch("coarsen_indices");
 }
 
 int launch_rotate_pixels(const float* src, const float* rot, int nrot, int n, float* dst,

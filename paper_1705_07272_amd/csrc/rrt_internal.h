@@ -60,6 +60,8 @@ struct RelightLaunch {
   unsigned flags;
   float* out;               // [F][V]
 };
+int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
+                           hipStream_t s);
 int launch_relight(const RelightLaunch& a, hipStream_t s);
 
 // Learned decoder (mlp.hip).

@@ -187,3 +187,14 @@ def test_mlp_validation(rrt):
     assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(0.9), f(0.999), f(1e-8), 0, None) == E.RRT_ERR_INVALID
     assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(1.0), f(0.999), f(1e-8), 1, None) == E.RRT_ERR_INVALID
     assert lib.rrt_adam_step(_p(0), None, _p(0), _p(0), _p(0), 0, f(1e-3), f(0.9), f(0.999), f(1e-8), 1, None) == E.RRT_OK
+
+
+def test_coarsen_validation(rrt):
+    lib, E = rrt.lib, rrt._abi
+    assert lib.rrt_coarsen_indices(_p(8), 10, 2, 1, _p(8), None) == E.RRT_ERR_INVALID    # n < 4
+    assert lib.rrt_coarsen_indices(_p(8), 10, 12, 1, _p(8), None) == E.RRT_ERR_INVALID   # not 2^k
+    assert lib.rrt_coarsen_indices(_p(8), 10, 16, 0, _p(8), None) == E.RRT_ERR_INVALID   # levels 0
+    assert lib.rrt_coarsen_indices(_p(8), 10, 16, 4, _p(8), None) == E.RRT_ERR_INVALID   # n' = 1
+    assert lib.rrt_coarsen_indices(_p(0), 10, 16, 2, _p(8), None) == E.RRT_ERR_INVALID   # null
+    assert lib.rrt_coarsen_indices(_p(0), 0, 16, 3, _p(0), None) == E.RRT_OK             # empty
+

@@ -334,3 +334,33 @@ def test_relight_workspace_reuse_and_determinism(rrt):
     a = run_relight(rrt, case)
     b = run_relight(rrt, case)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- coarse-level start (f3)
+@pytest.mark.parametrize("n,levels", [(4, 1), (16, 1), (64, 2), (128, 3), (1024, 9)])
+def test_coarsen_indices_exact(rrt, n, levels):
+    from oracle.levels import coarse_index
+    rng = np.random.default_rng(n + levels)
+    idx = rng.integers(-3, 6 * n * n + 3, size=20000).astype(np.int32)
+    got = rrt.coarsen_indices(dev(idx), n, levels).cpu().numpy()
+    assert np.array_equal(got, coarse_index(idx, n, levels))
+
+
+@pytest.mark.parametrize("n,levels,frames", [(64, 1, 1), (64, 2, 3), (128, 3, 1)])
+def test_relight_from_coarser_level(rrt, n, levels, frames):
+    """Relighting at n >> levels with remapped lighting and transport entries
+    against the checker's coarse-level start on the same stored inputs."""
+    from cases import build_case, frame_errors, workload
+    from oracle.levels import relight_from_level
+    w = workload(40 + n + levels, n, 1024, 40, 256, nframes=frames)
+    case = build_case(w)
+    ref = relight_from_level(case["light_idx"], case["light_val"], n, case["vert_rot"],
+                             case["frame_rot"], case["t_idx"], case["t_val"], levels)
+    nc = n >> levels
+    li = rrt.coarsen_indices(dev(case["light_idx"]), n, levels)
+    ti = rrt.coarsen_indices(dev(case["t_idx"]), n, levels)
+    out = rrt.relight(nc, li, dev(case["light_val"]), dev(case["vert_rot"]), ti,
+                      dev(case["t_val"]),
+                      frame_rot=None if case["frame_rot"] is None else dev(case["frame_rot"]))
+    assert max(frame_errors(out.cpu().numpy(), ref)) <= 1e-5
+

@@ -110,3 +110,25 @@ def test_constant_lighting_closed_form():
         dc = [f * n * n for f in range(6)]
         want = sum(n * c * tv[v][ti[v] == d].sum() for d in dc)
         assert abs(got[0, v] - want) <= 1e-10 * (1 + abs(want))
+
+
+def test_coarse_start_error_on_benchmark_scene():
+    """Measurement, not a pin: relative L2 error of starting the rotation 1,
+    2, 3 levels below the finest one on 40 vertices of the benchmark scene
+    (6 x 128^2, top-1024 lighting, CSR-256 Phong transport, random frames)
+    against the exact method.  Only a loose sanity bound is asserted: the
+    error need not grow monotonically with the skipped levels."""
+    from cases import build_case
+    from oracle.relight import rel_l2
+    from scenes.scene import WORKLOADS
+    w = WORKLOADS[2]
+    case = build_case(w, np.arange(0, 50000, 1250))
+    exact = relight(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
+                    case["t_idx"], case["t_val"])
+    errs = []
+    for k in (1, 2, 3):
+        approx = relight_from_level(case["light_idx"], case["light_val"], w.n, case["vert_rot"],
+                                    None, case["t_idx"], case["t_val"], k)
+        errs.append(rel_l2(approx[0], exact[0]))
+    print("coarse-level start rel-L2 (k = 1, 2, 3):", ["%.3e" % e for e in errs])
+    assert all(0.0 < e < 0.5 for e in errs)
