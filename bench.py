@@ -27,6 +27,10 @@ PEAK_HBM_GBS = 8000.0
 # Algorithmic 32-bit operations per rotated texel (exact integer source map
 # plus gather plus its share of the 2x2 levels); derivation in the design doc.
 OPS_PER_TEXEL = 36
+# The same count for the chain-rule rotation of the finest level: the exact
+# map, gather and chain rule once per 2x2 destination block, spread over its
+# four texels, plus the share of the levels above the finest one.
+CHAIN_OPS_PER_TEXEL = 25
 
 KERNEL_SOURCES = ["paper_1705_07272_amd/csrc/relight.hip", "paper_1705_07272_amd/csrc/geometry.h"]
 
@@ -249,6 +253,9 @@ def main():
     ap.add_argument("--start-level", type=int, default=0,
                     help="rotate from this many levels below the finest one (Sec. V.C remark; "
                          "an approximation of the exact method, 0 = exact)")
+    ap.add_argument("--chain-rule", action="store_true",
+                    help="rotate the finest level by the chain rule (Sec. V.A-V.B; an "
+                         "approximation of the exact method)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--mlp-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -307,7 +314,8 @@ def main():
         lv = rrt.convert(lv, "f16") if light_f16 else lv
         if L:
             li = rrt.coarsen_indices(li, n, L)
-        prep = rrt.prepare_lighting(n_rot, li[0], lv[0], workspace=ws)    # a3
+        prep = rrt.prepare_lighting(n_rot, li[0], lv[0], workspace=ws,   # a3
+                                    chain_rule=args.chain_rule)
         if ev is not None:
             ev[0].record()
         rrt.relight_prepared(prep, inp["rot"], inp["idx"], inp["val"], frame_rot=inp["frot"],
@@ -341,14 +349,15 @@ def main():
     hbm_bytes = (V * w.nnz * (4 + val_bytes) + V * 36 + F * V * 4
                  + (0 if inp["scale"] is None else inp["scale"].numel() * 4)
                  + (0 if inp["frot"] is None else F * 36))
-    achieved = texels * OPS_PER_TEXEL / (ms_kernel * 1e-3) / 1e12
+    ops_texel = CHAIN_OPS_PER_TEXEL if args.chain_rule else OPS_PER_TEXEL
+    achieved = texels * ops_texel / (ms_kernel * 1e-3) / 1e12
 
     traffic = None
     prof = os.path.join(ROOT, "profiles", f"relight_{w.name}_{args.form}_hbm.txt")
     if os.path.exists(prof):
         with open(prof) as fh:
             rec = json.load(fh)
-        if rec.get("kernel_fingerprint") == kernel_fingerprint():
+        if rec.get("kernel_fingerprint") == kernel_fingerprint() and not args.chain_rule:
             traffic = rec.get("hbm_bytes_per_launch")
 
     line = {
@@ -371,11 +380,14 @@ def main():
         **({"start_level": {"levels": L, "rotated_face": n_rot,
                             "note": "approximation; its error against the exact FP64 oracle "
                                     "is measured by tests/test_oracle_levels.py"}} if L else {}),
+        **({"chain_rule": {"note": "finest level rotated by the chain rule; an approximation "
+                                   "whose error against the exact FP64 oracle is measured by "
+                                   "tests/test_oracle_chain.py"}} if args.chain_rule else {}),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
                      "traffic": traffic, "kernel": "relight_kernel",
                      "kernel_ms": round(ms_kernel, 4), "rotated_texels": texels,
-                     "ops_per_texel": OPS_PER_TEXEL,
+                     "ops_per_texel": ops_texel,
                      "hbm_algorithmic_bytes": hbm_bytes,
                      "hbm_achieved_gbs": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9, 1),
                      "hbm_peak_gbs": PEAK_HBM_GBS},

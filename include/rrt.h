@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define RRT_ABI_VERSION 1
+#define RRT_ABI_VERSION 2
 
 typedef enum {
   RRT_OK = 0,
@@ -81,6 +81,11 @@ typedef enum {
 
 /* Flags of rrt_relight. */
 #define RRT_COMPENSATED 1u  /* Neumaier-compensated accumulation of the dot */
+#define RRT_CHAIN_RULE 2u   /* finest level rotated by the chain rule on the
+                               source's 2x2 blocks (Sec. V.A-V.B, eq:pde1 to
+                               eq:pde3) instead of the exact resampling; the
+                               coarser levels follow by the pyramid.  n >= 32
+                               only (else RRT_ERR_UNSUPPORTED). */
 
 int rrt_abi_version(void);
 const char* rrt_status_string(int status);
@@ -165,8 +170,10 @@ typedef struct {
    integer arithmetic (flooring shift). */
 
 /* Workspace: the reconstructed source map (6 n^2 values, float32 or
-   binary16) plus a 6 n^2 float32 staging buffer, 256-byte aligned.  Only
-   L->n and L->dtype matter for its size. */
+   binary16) plus a 6 n^2 float32 staging buffer (after prepare with
+   RRT_CHAIN_RULE: the source's 2x2 block coefficients, float32 (S, H, V, D)
+   per block), 256-byte aligned.  Only L->n and L->dtype matter for its
+   size. */
 int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
                           unsigned flags, size_t* bytes);
 /* radiance: [F][V] float32 (frame-major).  Equivalent to
@@ -177,11 +184,16 @@ int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport*
 /* The two halves of rrt_relight, for relighting many vertex batches or
    frame sets under one lighting:
    prepare  -- source reconstruction P = W^T L into the workspace (once per
-               lighting; Sec. V.B levels read in reverse);
+               lighting; Sec. V.B levels read in reverse); with
+               RRT_CHAIN_RULE in flags also the 2x2 block coefficients of P
+               that the chain rule reads (RRT_COMPENSATED is accepted and
+               ignored, so the flags of prepared may be passed as they are);
    prepared -- the per-vertex rotation and inner product reading P from a
-               workspace filled by prepare with the same L->n and L->dtype
-               (the workspace is only read, so several calls may share it). */
-int rrt_relight_prepare(const rrt_light* L, void* ws, size_t ws_bytes, void* stream);
+               workspace filled by prepare with the same L->n and L->dtype,
+               and with RRT_CHAIN_RULE if prepared is given it (the
+               workspace is only read, so several calls may share it). */
+int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_bytes,
+                        void* stream);
 int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
                          float* radiance, unsigned flags, const void* ws, size_t ws_bytes,
                          void* stream);

@@ -10,7 +10,7 @@ import ctypes
 import torch
 
 from . import _abi
-from ._abi import (RRT_BF16, RRT_BLOCK, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
+from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
                    RRT_S16, Light, RrtError, Rotations, Transport, check, lib)
 
 __all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight", "mlp_encode",
@@ -124,17 +124,21 @@ def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, blo
     return L, R, T
 
 
+def _flags(compensated, chain_rule):
+    return (RRT_COMPENSATED if compensated else 0) | (RRT_CHAIN_RULE if chain_rule else 0)
+
+
 def relight_workspace_bytes(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None,
-                            block_scale=None, compensated=False):
+                            block_scale=None, compensated=False, chain_rule=False):
     L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
-                                    RRT_COMPENSATED if compensated else 0, ctypes.byref(nbytes)))
+                                    _flags(compensated, chain_rule), ctypes.byref(nbytes)))
     return nbytes.value
 
 
 def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
-            compensated=False, out=None, workspace=None, cluster=None):
+            compensated=False, out=None, workspace=None, cluster=None, chain_rule=False):
     """radiance [F, V] float32.
 
     light_idx [k] int32, light_val [k] float32|float16; vert_rot [V, 3, 3]
@@ -143,10 +147,11 @@ def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, blo
     block-scaled forms with block_scale [V, ceil(nnz/64)];
     frame_rot [F, 3, 3] float32 or None.  With cluster [V] int32, t_idx is a
     per-cluster support table [C, nnz] and vertex v uses row cluster[v].
+    chain_rule: rotate the finest level by the chain rule (n >= 32).
     """
     L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
                            cluster)
-    flags = RRT_COMPENSATED if compensated else 0
+    flags = _flags(compensated, chain_rule)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
                                     ctypes.byref(nbytes)))
@@ -162,16 +167,18 @@ def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, blo
 
 class PreparedLighting:
     """Lighting whose source map P = W^T L has been reconstructed into a
-    device workspace by rrt_relight_prepare."""
+    device workspace by rrt_relight_prepare (with the chain rule's block
+    coefficients if chain_rule)."""
 
-    def __init__(self, n, light_idx, light_val, workspace):
+    def __init__(self, n, light_idx, light_val, workspace, chain_rule=False):
         self.n = n
         self.light_idx = light_idx
         self.light_val = light_val
         self.workspace = workspace
+        self.chain_rule = chain_rule
 
 
-def prepare_lighting(n, light_idx, light_val, workspace=None):
+def prepare_lighting(n, light_idx, light_val, workspace=None, chain_rule=False):
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -182,21 +189,22 @@ def prepare_lighting(n, light_idx, light_val, workspace=None):
                                     0, ctypes.byref(nbytes)))
     if workspace is None:
         workspace = _workspace(nbytes.value, light_idx.device)
-    check(lib.rrt_relight_prepare(ctypes.byref(L), _dev(workspace, "workspace"), workspace.numel(),
-                                  _stream()))
-    return PreparedLighting(n, light_idx, light_val, workspace)
+    check(lib.rrt_relight_prepare(ctypes.byref(L), _flags(False, chain_rule),
+                                  _dev(workspace, "workspace"), workspace.numel(), _stream()))
+    return PreparedLighting(n, light_idx, light_val, workspace, chain_rule)
 
 
 def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
                      compensated=False, out=None, cluster=None):
-    """relight() with a lighting already reconstructed by prepare_lighting()."""
+    """relight() with a lighting already reconstructed by prepare_lighting()
+    (the chain rule applies when the lighting was prepared for it)."""
     L, R, T = _descriptors(prep.n, prep.light_idx, prep.light_val, vert_rot, t_idx, t_val,
                            frame_rot, block_scale, cluster)
     if out is None:
         out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
     check(lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
                                    _dev(out, "out", torch.float32),
-                                   RRT_COMPENSATED if compensated else 0,
+                                   _flags(compensated, prep.chain_rule),
                                    _dev(prep.workspace, "workspace"), prep.workspace.numel(),
                                    _stream()))
     return out

@@ -22,6 +22,7 @@ RRT_S16 = 4
 RRT_BLOCK = 64
 
 RRT_COMPENSATED = 1
+RRT_CHAIN_RULE = 2
 
 RRT_MLP_IN = 128
 RRT_MLP_HIDDEN = 256
@@ -72,7 +73,7 @@ SIGNATURES = {
                                       P(c_size_t)]),
     "rrt_relight": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint, c_void_p,
                             c_size_t, c_void_p]),
-    "rrt_relight_prepare": (c_int, [P(Light), c_void_p, c_size_t, c_void_p]),
+    "rrt_relight_prepare": (c_int, [P(Light), c_uint, c_void_p, c_size_t, c_void_p]),
     "rrt_relight_prepared": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint,
                                      c_void_p, c_size_t, c_void_p]),
     "rrt_convert": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p]),

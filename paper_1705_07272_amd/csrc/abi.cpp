@@ -29,7 +29,8 @@ int check_launch(const char* what) {
 
 static bool valid_n(int n, int lo) { return n >= lo && n <= 1024 && is_pow2(n); }
 
-// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float|half]
+// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float|half];
+// after prepare the staging area holds the chain rule's 6 (n/2)^2 float4 blocks.
 struct RelightWs {
   size_t dense_off, src_off, total;
 };
@@ -204,8 +205,19 @@ int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_
   return RRT_OK;
 }
 
-int rrt_relight_prepare(const rrt_light* L, void* ws, size_t ws_bytes, void* stream) {
+static int check_relight_flags(const rrt_light* L, unsigned flags) {
+  if (flags & ~(RRT_COMPENSATED | RRT_CHAIN_RULE))
+    return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
+  if ((flags & RRT_CHAIN_RULE) && L->n < 32)
+    return fail(RRT_ERR_UNSUPPORTED, "relight: chain rule needs n >= 32 (n=%d)", L->n);
+  return RRT_OK;
+}
+
+int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_bytes,
+                        void* stream) {
   int st = validate_light(L);
+  if (st) return st;
+  st = check_relight_flags(L, flags);
   if (st) return st;
   const bool f16 = L->dtype == RRT_F16;
   const RelightWs w = relight_ws(L->n, f16);
@@ -217,8 +229,11 @@ int rrt_relight_prepare(const rrt_light* L, void* ws, size_t ws_bytes, void* str
   void* src = base + w.src_off;
   st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, dense, s);
   if (st) return st;
-  if (f16) return launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, s);
-  return launch_haar_inverse(dense, static_cast<float*>(src), L->n, 1, s);
+  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, s)
+           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 1, s);
+  if (st || !(flags & RRT_CHAIN_RULE)) return st;
+  // the staging buffer is free now: it takes the 2x2 block coefficients
+  return launch_source_blocks(src, f16, L->n, dense, s);
 }
 
 int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
@@ -226,7 +241,8 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
                          void* stream) {
   int st = validate_relight(L, R, T);
   if (st) return st;
-  if (flags & ~RRT_COMPENSATED) return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
+  st = check_relight_flags(L, flags);
+  if (st) return st;
   const bool f16 = L->dtype == RRT_F16;
   const RelightWs w = relight_ws(L->n, f16);
   st = check_ws(ws, ws_bytes, w.total, "relight");
@@ -250,6 +266,7 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
   a.n = L->n;
   a.flags = flags;
   a.out = radiance;
+  a.blocks = static_cast<const char*>(ws) + w.dense_off;
   return launch_relight(a, static_cast<hipStream_t>(stream));
 }
 
@@ -258,11 +275,12 @@ int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport*
   // validate everything before enqueueing anything
   int st = validate_relight(L, R, T);
   if (st) return st;
-  if (flags & ~RRT_COMPENSATED) return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
+  st = check_relight_flags(L, flags);
+  if (st) return st;
   st = check_ws(ws, ws_bytes, relight_ws(L->n, L->dtype == RRT_F16).total, "relight");
   if (st) return st;
   if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight: null radiance");
-  st = rrt_relight_prepare(L, ws, ws_bytes, stream);
+  st = rrt_relight_prepare(L, flags, ws, ws_bytes, stream);
   if (st) return st;
   return rrt_relight_prepared(L, R, T, radiance, flags, ws, ws_bytes, stream);
 }

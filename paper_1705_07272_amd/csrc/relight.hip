@@ -45,6 +45,7 @@ constexpr int kGroupBytes = 4096;
 // offsets (no 64-bit address arithmetic per texel) and hardware range
 // checking (reads past the map return 0).
 constexpr int kBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 template <typename SrcT>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const SrcT* p, int count) {
@@ -175,6 +176,7 @@ struct RelightParams {
   int comp;
   int listed;       // entries of each row listed in LDS: min(nnz, kMaxListed)
   int group_faces;  // faces whose block sums fit in LDS together
+  const float4* blocks;  // chain rule: (S, H, V, D) of every 2x2 source block
 };
 
 // Unscaled 2x2 levels with block side 2..T inside a thread's T x T tile, in
@@ -230,6 +232,63 @@ __device__ __forceinline__ int nth_face(unsigned faces, int k) {
   return face;
 }
 
+// Levels with block side From..T of a thread's tile (the smaller ones are
+// already in place), unscaled as in tile_levels.
+template <int T, int From>
+__device__ __forceinline__ void tile_levels_from(float (&g)[T][T]) {
+#pragma unroll
+  for (int B = From; B <= T; B <<= 1) {
+#pragma unroll
+    for (int r0 = 0; r0 < T; r0 += B)
+#pragma unroll
+      for (int c0 = 0; c0 < T; c0 += B) {
+        const int h = B / 2;
+        const float a = g[r0][c0], b = g[r0][c0 + h], c = g[r0 + h][c0], d = g[r0 + h][c0 + h];
+        g[r0][c0] = (a + b) + (c + d);
+        g[r0][c0 + h] = (a - b) + (c - d);
+        g[r0 + h][c0] = (a + b) - (c + d);
+        g[r0 + h][c0 + h] = (a - b) - (c - d);
+      }
+  }
+}
+
+// In-face and major components (sc, tc, D) of v for source face f:
+//   +X (-z,-y, x)  -X (z,-y,-x)  +Y (x, z, y)  -Y (x,-z,-y)  +Z (x,-y, z)  -Z (-x,-y,-z)
+__device__ __forceinline__ float3 face_components(int f, float x, float y, float z) {
+  const int a = f >> 1;
+  const bool neg = (f & 1) != 0;
+  const float sc = a == 0 ? (neg ? z : -z) : (f == 5 ? -x : x);
+  const float tc = a == 1 ? (neg ? -z : z) : -y;
+  const float D = a == 0 ? x : (a == 1 ? y : z);
+  return make_float3(sc, tc, neg ? -D : D);
+}
+
+// Chain-rule rotation of one destination 2x2 block (Sec. V.A-V.B,
+// eq:pde1-eq:pde3): c = (S, H, V, D) of its source block (face sf), d the
+// block centre's direction and ex, ey its change per texel step in x and y
+// (all in the same units).  Returns the unscaled level-1 coefficients
+// (2 S, 2 H, 2 V, 2 D) of the destination block.
+__device__ __forceinline__ float4 chain_block(float4 c, int sf, float3 d, float3 ex, float3 ey,
+                                              float h) {
+  const float3 p = face_components(sf, d.x, d.y, d.z);
+  const float3 px = face_components(sf, ex.x, ex.y, ex.z);
+  const float3 py = face_components(sf, ey.x, ey.y, ey.z);
+  const float iD = __builtin_amdgcn_rcpf(p.z);
+  const float iD2 = iD * iD;
+  // x' = h (sc / D + 1), y' = h (tc / D + 1)
+  const float xx = h * (px.x * p.z - p.x * px.z) * iD2;
+  const float xy = h * (py.x * p.z - p.x * py.z) * iD2;
+  const float yx = h * (px.y * p.z - p.y * px.z) * iD2;
+  const float yy = h * (py.y * p.z - p.y * py.z) * iD2;
+  const float xxy = h * (2.0f * p.x * px.z * py.z * iD - (px.x * py.z + py.x * px.z)) * iD2;
+  const float yxy = h * (2.0f * p.y * px.z * py.z * iD - (px.y * py.z + py.y * px.z)) * iD2;
+  const float fx = -c.y, fy = -c.z, fxy = 2.0f * c.w;
+  const float gx = fx * xx + fy * yx;
+  const float gy = fx * xy + fy * yy;
+  const float gxy = fxy * (xx * yy + xy * yx) + fx * xxy + fy * yxy;
+  return make_float4(2.0f * c.x, -2.0f * gx, -2.0f * gy, gxy);
+}
+
 // Where a transport entry is consumed when the faces of rank [g0, g0 + FG)
 // among `faces` are processed together.  Block gi = (face rank - g0) G^2 +
 // block row * G + block column holds every coefficient of a block at most Q
@@ -258,7 +317,9 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
 }
 
 // Q: block side (min(n, kBlock)); the wave's TS x TS lanes each own a T x T tile.
-template <int Q, typename SrcT>
+// CHAIN: the finest level comes from the chain rule on the source blocks
+// (Q = 32 only) instead of the exact resampling.
+template <int Q, typename SrcT, bool CHAIN>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
   constexpr int T = Q / TS;           // texels per tile side
@@ -359,13 +420,64 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         const int lx = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
         const int ly = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
         const int lz = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
+        // chain rule: the lane's destination block (ty, tx) at half resolution
+        const int hn = n >> 1;
+        const int Uh = 2 * tx + 1 - hn, Vh = 2 * ty + 1 - hn;
+        const int hx = wrap_mad(ax.mU.x, Uh, wrap_mad(ax.mV.x, Vh, wrap_mad(ax.mN.x, hn, 0)));
+        const int hy = wrap_mad(ax.mU.y, Uh, wrap_mad(ax.mV.y, Vh, wrap_mad(ax.mN.y, hn, 0)));
+        const int hz = wrap_mad(ax.mU.z, Uh, wrap_mad(ax.mV.z, Vh, wrap_mad(ax.mN.z, hn, 0)));
         for (int by = 0; by < G; ++by) {
           for (int bx = 0; bx < G; ++bx, ++gi) {
+            if constexpr (CHAIN) {
+              // Destination 2x2 blocks (8 a + ty, 8 b + tx) of the 16 x 16 in
+              // this block: the source block by the exact map at n / 2, then
+              // the chain rule; level-1 coefficients go straight to the image.
+              const __amdgpu_buffer_rsrc_t blk = __builtin_amdgcn_make_buffer_rsrc(
+                  const_cast<float4*>(p.blocks), short(0), 6 * hn * hn * 16, kBufferWord3);
+              const float eps_h = quotient_margin(logn - 1);
+              const int rx = wrap_mad(ax.mU.x, 2 * (Q / 2) * bx, wrap_mad(ax.mV.x, 2 * (Q / 2) * by, hx));
+              const int ry = wrap_mad(ax.mU.y, 2 * (Q / 2) * bx, wrap_mad(ax.mV.y, 2 * (Q / 2) * by, hy));
+              const int rz = wrap_mad(ax.mU.z, 2 * (Q / 2) * bx, wrap_mad(ax.mV.z, 2 * (Q / 2) * by, hz));
+              float4 cf[2][2];
+              int sf[2][2];
+#pragma unroll
+              for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                  const int dx = wrap_mad(ax.mU.x, 16 * b, wrap_mad(ax.mV.x, 16 * a, rx));
+                  const int dy = wrap_mad(ax.mU.y, 16 * b, wrap_mad(ax.mV.y, 16 * a, ry));
+                  const int dz = wrap_mad(ax.mU.z, 16 * b, wrap_mad(ax.mV.z, 16 * a, rz));
+                  const unsigned at = source_texel_scaled<4>(dx, dy, dz, logn - 1, eps_h);
+                  sf[a][b] = int(at >> (2 * (logn - 1) + 4));
+                  const u32x4_t raw = __builtin_amdgcn_raw_buffer_load_b128(blk, int(at), 0, 0);
+                  cf[a][b] = make_float4(__uint_as_float(raw.x), __uint_as_float(raw.y),
+                                         __uint_as_float(raw.z), __uint_as_float(raw.w));
+                }
+              const float3 ex = make_float3(2.0f * float(ax.mU.x), 2.0f * float(ax.mU.y),
+                                            2.0f * float(ax.mU.z));
+              const float3 ey = make_float3(2.0f * float(ax.mV.x), 2.0f * float(ax.mV.y),
+                                            2.0f * float(ax.mV.z));
+#pragma unroll
+              for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                  // the block centre at full resolution: twice the half-resolution direction
+                  const int dx = wrap_mad(ax.mU.x, 16 * b, wrap_mad(ax.mV.x, 16 * a, rx));
+                  const int dy = wrap_mad(ax.mU.y, 16 * b, wrap_mad(ax.mV.y, 16 * a, ry));
+                  const int dz = wrap_mad(ax.mU.z, 16 * b, wrap_mad(ax.mV.z, 16 * a, rz));
+                  const float3 dc = make_float3(2.0f * float(dx), 2.0f * float(dy), 2.0f * float(dz));
+                  const float4 o = chain_block(cf[a][b], sf[a][b], dc, ex, ey, float(hn));
+                  const int r0 = 2 * (8 * a + ty), c0 = 2 * (8 * b + tx);
+                  img[r0 * STRIDE + c0] = o.x;
+                  img[r0 * STRIDE + c0 + 1] = o.y;
+                  img[(r0 + 1) * STRIDE + c0] = o.z;
+                  img[(r0 + 1) * STRIDE + c0 + 1] = o.w;
+                }
+            } else if (owns_tile) {
             // Gather in TS x TS patches of adjacent texels (one load instruction
             // covers a compact patch, which the L1 serves with few cache lines):
             // lane (ty, tx) takes texel (TS a + ty, TS b + tx) of every patch
             // (a, b) and stores it raw into the block image.
-            if (owns_tile) {
               int rx = wrap_mad(ax.mU.x, 2 * Q * bx, wrap_mad(ax.mV.x, 2 * Q * by, lx));
               int ry = wrap_mad(ax.mU.y, 2 * Q * bx, wrap_mad(ax.mV.y, 2 * Q * by, ly));
               int rz = wrap_mad(ax.mU.z, 2 * Q * bx, wrap_mad(ax.mV.z, 2 * Q * by, lz));
@@ -402,7 +514,11 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
 #pragma unroll
                 for (int cc = 0; cc < T; ++cc)
                   g[rr][cc] = img[(ty * T + rr) * STRIDE + tx * T + cc];
-              tile_levels<T>(g);
+              if constexpr (CHAIN) {
+                tile_levels_from<T, 4>(g);
+              } else {
+                tile_levels<T>(g);
+              }
 #pragma unroll
               for (int rr = 0; rr < T; ++rr)
 #pragma unroll
@@ -515,6 +631,22 @@ __global__ void scatter_light(const int32_t* __restrict__ idx, const void* __res
                   : static_cast<const float*>(val)[i];
 }
 
+// Orthonormal (S, H, V, D) of every 2x2 block of the source map, for the
+// chain-rule rotation: blocks[face][bi][bj].
+template <typename SrcT>
+__global__ void source_blocks_kernel(const SrcT* __restrict__ src, int logn,
+                                     float4* __restrict__ blocks) {
+  const int hl = logn - 1;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 6 << (2 * hl)) return;
+  const int f = q >> (2 * hl), bi = (q >> hl) & ((1 << hl) - 1), bj = q & ((1 << hl) - 1);
+  const int at = (f << (2 * logn)) + ((2 * bi) << logn) + 2 * bj;
+  const float a = float(src[at]), b = float(src[at + 1]);
+  const float c = float(src[at + (1 << logn)]), d = float(src[at + (1 << logn) + 1]);
+  blocks[q] = make_float4(0.5f * ((a + b) + (c + d)), 0.5f * ((a - b) + (c - d)),
+                          0.5f * ((a + b) - (c + d)), 0.5f * ((a - b) - (c - d)));
+}
+
 // Index of coefficient idx at resolution n in the map n >> levels, or -1 for
 // the `levels` finest levels (Mallat layout: the coarse levels are the
 // top-left corner of each face).
@@ -557,18 +689,19 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   dst[int64_t(r) * 6 * per_face + q] = src[min(at, unsigned(6 * per_face - 1))];
 }
 
-template <int Q, typename SrcT>
+template <int Q, typename SrcT, bool CHAIN = false>
 int launch_q(const RelightParams& prm, int64_t nvert, hipStream_t s) {
   const int G = (1 << prm.logn) / Q;
   const size_t lds = ((size_t(Q) * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) & ~size_t(7)) +
                      size_t(prm.group_faces) * G * G * 8;
-  hipLaunchKernelGGL((relight_kernel<Q, SrcT>), dim3(unsigned(nvert)), dim3(kThreads), lds, s,
-                     prm);
+  hipLaunchKernelGGL((relight_kernel<Q, SrcT, CHAIN>), dim3(unsigned(nvert)), dim3(kThreads), lds,
+                     s, prm);
   return check_launch("relight_kernel");
 }
 
 template <typename SrcT>
-int launch_src(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
+int launch_src(const RelightParams& prm, int n, int64_t nvert, bool chain, hipStream_t s) {
+  if (chain) return launch_q<kBlock, SrcT, true>(prm, nvert, s);
   switch (n < kBlock ? n : kBlock) {
     case 2: return launch_q<2, SrcT>(prm, nvert, s);
     case 4: return launch_q<4, SrcT>(prm, nvert, s);
@@ -602,7 +735,10 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   const int G = a.n < kBlock ? 1 : a.n / kBlock;
   const int fit = kGroupBytes / (G * G * 8);
   p.group_faces = fit < 1 ? 1 : (fit > 6 ? 6 : fit);
-  return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, s) : launch_src<float>(p, a.n, a.nvert, s);
+  p.blocks = static_cast<const float4*>(a.blocks);
+  const bool chain = (a.flags & RRT_CHAIN_RULE) != 0;
+  return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, chain, s)
+                   : launch_src<float>(p, a.n, a.nvert, chain, s);
 }
 
 int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n,
@@ -614,6 +750,20 @@ int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, 
   hipLaunchKernelGGL(scatter_light, dim3(unsigned((k + 255) / 256)), dim3(256), 0, s, idx, val,
                      dtype == RRT_F16 ? 1 : 0, k, int(total), dense);
   return check_launch("scatter_light");
+}
+
+int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStream_t s) {
+  const int total = 6 * (n / 2) * (n / 2);
+  if (f16) {
+    hipLaunchKernelGGL(source_blocks_kernel<__half>, dim3(unsigned((total + 255) / 256)), dim3(256),
+                       0, s, static_cast<const __half*>(src), ilog2(n),
+                       reinterpret_cast<float4*>(blocks));
+  } else {
+    hipLaunchKernelGGL(source_blocks_kernel<float>, dim3(unsigned((total + 255) / 256)), dim3(256),
+                       0, s, static_cast<const float*>(src), ilog2(n),
+                       reinterpret_cast<float4*>(blocks));
+  }
+  return check_launch("source_blocks");
 }
 
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,

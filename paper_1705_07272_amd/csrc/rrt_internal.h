@@ -59,7 +59,9 @@ struct RelightLaunch {
   int n;
   unsigned flags;
   float* out;               // [F][V]
+  const void* blocks;       // chain rule: float4 (S, H, V, D) per 2x2 source block
 };
+int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStream_t s);
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
                            hipStream_t s);
 int launch_relight(const RelightLaunch& a, hipStream_t s);

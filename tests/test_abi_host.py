@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(rrt):
 
 def test_version_and_strings(rrt):
     lib = rrt.lib
-    assert lib.rrt_abi_version() == 1
+    assert lib.rrt_abi_version() == 2
     assert lib.rrt_status_string(0) == b"ok"
     assert lib.rrt_status_string(3) == b"workspace too small"
     assert lib.rrt_status_string(99) == b"unknown status"
@@ -147,6 +147,16 @@ def test_relight_validation(rrt):
                            1 << 20, None) == E.RRT_ERR_INVALID                 # null radiance
     assert lib.rrt_relight(None, ctypes.byref(R), ctypes.byref(T), _p(8), 0, _p(256), 1 << 20,
                            None) == E.RRT_ERR_INVALID
+    # chain rule: n >= 32 only, checked before anything is enqueued
+    assert lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8),
+                           E.RRT_CHAIN_RULE, _p(256), 1 << 20, None) == E.RRT_ERR_UNSUPPORTED
+    assert lib.rrt_relight_prepare(ctypes.byref(L), E.RRT_CHAIN_RULE, _p(256), 1 << 20,
+                                   None) == E.RRT_ERR_UNSUPPORTED
+    assert lib.rrt_relight_prepare(ctypes.byref(L), 8, _p(256), 1 << 20,
+                                   None) == E.RRT_ERR_INVALID
+    assert lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8),
+                                    E.RRT_CHAIN_RULE | E.RRT_COMPENSATED, _p(256), 1 << 20,
+                                    None) == E.RRT_ERR_UNSUPPORTED
 
 
 def test_convert_validation(rrt):

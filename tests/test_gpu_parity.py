@@ -364,3 +364,67 @@ def test_relight_from_coarser_level(rrt, n, levels, frames):
                       frame_rot=None if case["frame_rot"] is None else dev(case["frame_rot"]))
     assert max(frame_errors(out.cpu().numpy(), ref)) <= 1e-5
 
+
+
+# ---------------------------------------------------------------- chain rule (f1)
+def chain_reference(case):
+    """The checker's chain-rule radiance [F, V] and its magnitude scale
+    sum_k |T_k ghat_k| (FP64)."""
+    from oracle.chain import chain_rotate
+    from oracle.haar import haar_forward
+    from oracle.relight import frame_vertex_rotation, reconstruct_lighting
+    n = case["n"]
+    P = reconstruct_lighting(case["light_idx"], case["light_val"], n)
+    V = case["vert_rot"].shape[0]
+    F = 1 if case["frame_rot"] is None else case["frame_rot"].shape[0]
+    ref = np.zeros((F, V))
+    scale = np.zeros((F, V))
+    for v in range(V):
+        idx = case["t_idx"][v].astype(np.int64)
+        tv = case["t_val"][v].astype(np.float64)
+        for f in range(F):
+            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], v, f)
+            g = haar_forward(chain_rotate(P, Rq)).ravel()[idx]
+            ref[f, v] = np.dot(tv, g)
+            scale[f, v] = np.abs(tv * g).sum()
+    return ref, scale
+
+
+@pytest.mark.parametrize("n,nframes,compensated", [(32, 1, False), (64, 3, True), (128, 1, False)])
+def test_relight_chain_rule(rrt, n, nframes, compensated):
+    """Chain-rule rotation of the finest level against the checker's
+    chain_rotate on the same stored inputs (workload-shaped scenes)."""
+    from cases import build_case, workload
+    w = workload(600 + n, n, 1024, 37, 256, nframes=nframes)
+    case = build_case(w)
+    got = run_relight(rrt, case, compensated=compensated, chain_rule=True)
+    check_frames(got, chain_reference(case))
+
+
+def test_relight_chain_rule_prepared_and_cube_rotations(rrt):
+    """prepare + prepared with the chain rule equals the one-call form bit for
+    bit; under cube-group rotations (where the mapping is a permutation of
+    whole blocks) the chain rule equals the exact method."""
+    from cases import build_case, reference, workload
+    from oracle.chain import FACE_AXES
+    n = 64
+    w = workload(640, n, 1024, 24, 256)
+    case = build_case(w)
+    # 24 cube-group rotations: signed permutation matrices of determinant 1
+    rots = []
+    import itertools
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product([1, -1], repeat=3):
+            M = np.zeros((3, 3))
+            for r in range(3):
+                M[r, perm[r]] = signs[r]
+            if np.linalg.det(M) > 0:
+                rots.append(M)
+    assert len(rots) == 24 and FACE_AXES.shape == (6, 3, 3)
+    case = dict(case, vert_rot=np.stack(rots).astype(np.float32))
+    one = run_relight(rrt, case, chain_rule=True)
+    check_frames(one, reference(case, return_scale=True))
+    prep = rrt.prepare_lighting(n, dev(case["light_idx"]), dev(case["light_val"]), chain_rule=True)
+    two = rrt.relight_prepared(prep, dev(case["vert_rot"]), dev(case["t_idx"]), dev(case["t_val"]))
+    torch.cuda.synchronize()
+    assert np.array_equal(one, two.cpu().numpy())

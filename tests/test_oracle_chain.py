@@ -90,3 +90,23 @@ def test_relight_chain_equals_relight_for_cube_rotations():
     R = np.stack(_cube_group()[5:8]).astype(np.float32)
     np.testing.assert_allclose(relight_chain(li, lv, n, R, None, ti, tv),
                                relight(li, lv, n, R, None, ti, tv), rtol=1e-12, atol=1e-12)
+
+
+def test_chain_rule_error_on_benchmark_scene():
+    """Measurement, not a pin: relative L2 error of the chain-rule rotation on
+    40 vertices of the benchmark scene (6 x 128^2, top-1024 lighting, CSR-256
+    Phong transport) against the exact method.  The first-order rule drops
+    the second derivatives that a sharp HDR lighting has, so only a loose
+    sanity bound is asserted."""
+    from cases import build_case
+    from oracle.relight import rel_l2
+    from scenes.scene import WORKLOADS
+    w = WORKLOADS[2]
+    case = build_case(w, np.arange(0, 50000, 1250))
+    exact = relight(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
+                    case["t_idx"], case["t_val"])
+    approx = relight_chain(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
+                           case["t_idx"], case["t_val"])
+    e = rel_l2(approx[0], exact[0])
+    print("chain-rule rel-L2 on the benchmark scene: %.3e" % e)
+    assert 0.0 < e < 0.5
