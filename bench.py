@@ -253,6 +253,9 @@ def main():
     ap.add_argument("--start-level", type=int, default=0,
                     help="rotate from this many levels below the finest one (Sec. V.C remark; "
                          "an approximation of the exact method, 0 = exact)")
+    ap.add_argument("--nnz", type=int, default=0,
+                    help="transport coefficients kept per vertex (budget sweep; 0 = the "
+                         "workload's own)")
     ap.add_argument("--chain-rule", action="store_true",
                     help="rotate the finest level by the chain rule (Sec. V.A-V.B; an "
                          "approximation of the exact method)")
@@ -268,11 +271,17 @@ def main():
               "(the path needs no collective; vertices shard trivially)", file=sys.stderr)
         sys.exit(2)
 
+    import dataclasses
+
     from scenes.scene import WORKLOADS
     w = WORKLOADS[args.workload]
+    if args.nnz:
+        w = dataclasses.replace(w, nnz=args.nnz)
 
     base = None
-    if not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp":
+    # the oracle baseline is of the workload as configured (no budget override)
+    if (not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp"
+            and not args.nnz):
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
         base = cpu_baseline(args.workload, args.cpu_sample, workers)
         print(f"cpu baseline done: {base['sample']}", file=sys.stderr, flush=True)
@@ -357,7 +366,9 @@ def main():
     if os.path.exists(prof):
         with open(prof) as fh:
             rec = json.load(fh)
-        if rec.get("kernel_fingerprint") == kernel_fingerprint() and not args.chain_rule:
+        # counters were taken on the workload as configured, exact method
+        if (rec.get("kernel_fingerprint") == kernel_fingerprint() and not args.chain_rule
+                and not args.nnz and not L):
             traffic = rec.get("hbm_bytes_per_launch")
 
     line = {

@@ -132,3 +132,29 @@ def test_coarse_start_error_on_benchmark_scene():
         errs.append(rel_l2(approx[0], exact[0]))
     print("coarse-level start rel-L2 (k = 1, 2, 3):", ["%.3e" % e for e in errs])
     assert all(0.0 < e < 0.5 for e in errs)
+
+
+def test_transport_budget_error_on_benchmark_scene():
+    """Measurement, not a pin: relative L2 error of keeping only the m
+    largest transport coefficients per vertex (m = 4, 16, 64, 256; the
+    coefficient budgets of Sec. VI) on 40 vertices of the benchmark scene
+    against the untruncated transport (all 6 n^2 coefficients), both with the
+    exact rotation.  The error must shrink as the budget grows."""
+    import dataclasses
+
+    from cases import build_case, stored_transport
+    from oracle.relight import rel_l2
+    from scenes.scene import WORKLOADS
+    w = WORKLOADS[2]
+    vids = np.arange(0, 50000, 1250)
+    case = build_case(w, vids)
+    wd = dataclasses.replace(w, nnz=6 * w.n * w.n)
+    _, dense = stored_transport(wd, vids)
+    full = relight(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None, None, dense)
+    errs = []
+    for m in (4, 16, 64, 256):
+        ti, tv = stored_transport(dataclasses.replace(w, nnz=m), vids)
+        got = relight(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None, ti, tv)
+        errs.append(rel_l2(got[0], full[0]))
+    print("\ntransport budget rel-L2 (m = 4, 16, 64, 256):", ["%.3e" % e for e in errs])
+    assert all(a > b for a, b in zip(errs, errs[1:]))
