@@ -155,6 +155,23 @@ def triple_pixels(a, b, c, n):
     return float(np.sum(A * B * C))
 
 
+def magnitude_map(idx, val, n):
+    """sum_i |val_i| |Psi_i(q)| per texel [6, n, n]: the magnitude against
+    which a finite-precision reconstruction of the map rounds (|Psi_i| is 1/B
+    on the square of side B of function i)."""
+    c = np.zeros(6 * n * n)
+    np.add.at(c, np.asarray(idx, np.int64), np.abs(np.asarray(val, np.float64)))
+    c = c.reshape(6, n, n)
+    out = np.full((6, n, n), 1.0) * (c[:, :1, :1] / n)
+    g = 1                                     # coefficient grid side of the level
+    while g < n:
+        B = n // g
+        lvl = c[:, :g, g:2 * g] + c[:, g:2 * g, :g] + c[:, g:2 * g, g:2 * g]
+        out += np.repeat(np.repeat(lvl, B, axis=1), B, axis=2) / B
+        g *= 2
+    return out
+
+
 def relight_triple(light_idx, light_val, n, vert_rot, frame_rot, v_idx, v_val, brdf_pix,
                    material=None, vertices=None, frames=None, return_scale=False):
     """radiance[f][v] (FP64) of the triple product: the exactly rotated
@@ -162,8 +179,10 @@ def relight_triple(light_idx, light_val, n, vert_rot, frame_rot, v_idx, v_val, b
     brdf_pix[material[v]] (pixel-domain, local frame, [M, 6, n, n]) and the
     stored visibility row c = (v_idx[v], v_val[v]).  A material outside
     [0, M) gives 0.  With return_scale, also the magnitude scale
-    sum_k |c_k| (1/B_k) sum_{q in square k} |A(q) B(q)| of each result (a
-    bound on every term of the texel-domain evaluation)."""
+    sum_k |c_k| (1/B_k) sum_{q in square k} |A|(q) |B(q)| of each result,
+    |A| the rotated magnitude_map of the lighting: a bound on every term of
+    the texel-domain evaluation, the reconstruction of the lighting
+    included."""
     brdf_pix = np.asarray(brdf_pix, np.float64).reshape(-1, 6, n, n)
     M = brdf_pix.shape[0]
     V = np.asarray(vert_rot).shape[0]
@@ -171,6 +190,7 @@ def relight_triple(light_idx, light_val, n, vert_rot, frame_rot, v_idx, v_val, b
     vertices = np.arange(V) if vertices is None else np.asarray(vertices)
     frames = np.arange(nf) if frames is None else np.asarray(frames)
     P = reconstruct_lighting(light_idx, light_val, n)
+    Pmag = magnitude_map(light_idx, light_val, n) if return_scale else None
     bcoef = [haar_forward(brdf_pix[m]).ravel() for m in range(M)]
     tables = _face_tables(n)
     K, Z, R0, C0 = tables
@@ -187,7 +207,7 @@ def relight_triple(light_idx, light_val, n, vert_rot, frame_rot, v_idx, v_val, b
             A = rotate_pixels(P, Rq)
             out[bi, ai] = triple_sum(haar_forward(A).ravel(), bcoef[m], ci, cv, n, tables)
             if return_scale:
-                AB = np.abs(A * brdf_pix[m])
+                AB = rotate_pixels(Pmag, Rq) * np.abs(brdf_pix[m])
                 sat = np.zeros((6, n + 1, n + 1))
                 sat[:, 1:, 1:] = AB.cumsum(1).cumsum(2)
                 ok = (ci >= 0) & (ci < 6 * n * n)

@@ -13,7 +13,8 @@ import pytest
 
 from oracle.haar import haar_forward, haar_inverse
 from oracle.relight import relight
-from oracle.triple import relight_triple, triple_pixels, triple_sum, tripling_coefficient
+from oracle.triple import (magnitude_map, relight_triple, triple_pixels, triple_sum,
+                           tripling_coefficient)
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
@@ -136,3 +137,15 @@ def test_invalid_material_gives_zero_and_scale_bounds_terms():
                                 return_scale=True)
     assert out[0, 1] == 0.0 and out[0, 2] == 0.0 and abs(out[0, 0]) > 0
     assert abs(out[0, 0]) <= scale[0, 0]
+
+
+def test_magnitude_map_is_the_absolute_basis_sum():
+    """magnitude_map = sum_i |v_i| |Psi_i| with the basis functions taken from
+    the pinned inverse transform."""
+    n = 4
+    Bm = _basis_matrix(n)
+    rng = np.random.default_rng(4)
+    idx = rng.choice(6 * n * n, 50, replace=False)
+    val = rng.normal(size=50)
+    want = (np.abs(val)[:, None] * np.abs(Bm[idx])).sum(0).reshape(6, n, n)
+    np.testing.assert_allclose(magnitude_map(idx, val, n), want, rtol=1e-13, atol=1e-13)
