@@ -24,13 +24,16 @@ sys.path.insert(0, ROOT)
 
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.32 T non-packed 32-bit lane-ops/s
 PEAK_HBM_GBS = 8000.0
-# Algorithmic 32-bit operations per rotated texel (exact integer source map
-# plus gather plus its share of the 2x2 levels); derivation in the design doc.
-OPS_PER_TEXEL = 36
+# Algorithmic operations per rotated texel: the gfx950 instructions the
+# exact source map, the gather and the texel's share of the 2x2 levels need
+# (one per VALU instruction or memory access); derivation in the design doc.
+OPS_PER_TEXEL = 27
 # The same count for the chain-rule rotation of the finest level: the exact
 # map, gather and chain rule once per 2x2 destination block, spread over its
 # four texels, plus the share of the levels above the finest one.
-CHAIN_OPS_PER_TEXEL = 25
+CHAIN_OPS_PER_TEXEL = 21
+# The triple product adds the read of the BRDF factor and the product.
+TRIPLE_EXTRA_OPS = 2
 
 KERNEL_SOURCES = ["paper_1705_07272_amd/csrc/relight.hip", "paper_1705_07272_amd/csrc/geometry.h"]
 
@@ -101,13 +104,17 @@ def cpu_baseline(cfg, sample, workers):
 # ----------------------------------------------------------------------------
 # Device inputs
 # ----------------------------------------------------------------------------
-def device_inputs(w, form, batch=2048):
+def device_inputs(w, form, batch=2048, materials=0):
+    """Device-resident inputs of the workload.  With materials > 0 the rows
+    are the vertices' visibility (triple product) and the materials' BRDF
+    factors and the vertices' material ids are added."""
     import numpy as np
     import torch
 
     import paper_1705_07272_amd as rrt
-    from scenes.scene import (frame_rotations, lighting_pixels, phong_exponents,
-                              transport_pixels_torch, vertex_rotations)
+    from scenes.scene import (brdf_pixels, frame_rotations, lighting_pixels, material_ids,
+                              phong_exponents, transport_pixels_torch, vertex_rotations,
+                              visibility_torch)
     dev = torch.device("cuda")
     pix = torch.from_numpy(lighting_pixels(w.cfg, w.n)).to(dev)
     rot = torch.from_numpy(np.ascontiguousarray(vertex_rotations(w))).to(dev)
@@ -118,7 +125,10 @@ def device_inputs(w, form, batch=2048):
     val = torch.empty((w.nverts, w.nnz), dtype=torch.float32, device=dev)
     for s in range(0, w.nverts, batch):
         e = min(w.nverts, s + batch)
-        T = transport_pixels_torch(w, exps[s:e], np.arange(s, e), dev, dtype=torch.float32)
+        if materials:
+            T = visibility_torch(w, np.arange(s, e), dev).to(torch.float32)
+        else:
+            T = transport_pixels_torch(w, exps[s:e], np.arange(s, e), dev, dtype=torch.float32)
         i, v = rrt.project_rows(T.contiguous(), w.nnz)
         idx[s:e] = i
         val[s:e] = v
@@ -128,8 +138,13 @@ def device_inputs(w, form, batch=2048):
         val = rrt.convert(val, "bf16")
     elif form in ("e4m3", "s16"):
         val, scale = rrt.convert(val, form)
+    brdf = mat = None
+    if materials:
+        brdf = torch.from_numpy(brdf_pixels(w, materials).astype(np.float32)).to(dev)
+        mat = torch.from_numpy(material_ids(w, materials)).to(dev)
     torch.cuda.synchronize()
-    return dict(pix=pix, rot=rot, frot=frot, idx=idx, val=val, scale=scale)
+    return dict(pix=pix, rot=rot, frot=frot, idx=idx, val=val, scale=scale, brdf=brdf,
+                material=mat)
 
 
 def run_learned(args, w):
@@ -256,6 +271,9 @@ def main():
     ap.add_argument("--nnz", type=int, default=0,
                     help="transport coefficients kept per vertex (budget sweep; 0 = the "
                          "workload's own)")
+    ap.add_argument("--triple", type=int, default=0, metavar="M",
+                    help="triple product with M materials: BRDF factors per material, the "
+                         "rows hold each vertex's visibility (Sec. III)")
     ap.add_argument("--chain-rule", action="store_true",
                     help="rotate the finest level by the chain rule (Sec. V.A-V.B; an "
                          "approximation of the exact method)")
@@ -281,7 +299,7 @@ def main():
     base = None
     # the oracle baseline is of the workload as configured (no budget override)
     if (not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp"
-            and not args.nnz):
+            and not args.nnz and not args.triple):
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
         base = cpu_baseline(args.workload, args.cpu_sample, workers)
         print(f"cpu baseline done: {base['sample']}", file=sys.stderr, flush=True)
@@ -304,7 +322,7 @@ def main():
         run_learned(args, WORKLOADS[4] if args.workload == 2 else w)
         return
 
-    inp = device_inputs(w, args.form)
+    inp = device_inputs(w, args.form, materials=args.triple)
     print("inputs ready", file=sys.stderr, flush=True)
     n, K, V = w.n, w.k_light, w.nverts
     L = args.start_level
@@ -328,7 +346,8 @@ def main():
         if ev is not None:
             ev[0].record()
         rrt.relight_prepared(prep, inp["rot"], inp["idx"], inp["val"], frame_rot=inp["frot"],
-                             block_scale=inp["scale"], compensated=light_f16, out=out)
+                             block_scale=inp["scale"], compensated=light_f16, out=out,
+                             brdf=inp["brdf"], material=inp["material"])
         if ev is not None:
             ev[1].record()
 
@@ -357,19 +376,22 @@ def main():
     val_bytes = inp["val"].element_size()
     hbm_bytes = (V * w.nnz * (4 + val_bytes) + V * 36 + F * V * 4
                  + (0 if inp["scale"] is None else inp["scale"].numel() * 4)
-                 + (0 if inp["frot"] is None else F * 36))
-    ops_texel = CHAIN_OPS_PER_TEXEL if args.chain_rule else OPS_PER_TEXEL
+                 + (0 if inp["frot"] is None else F * 36)
+                 + (0 if inp["brdf"] is None else inp["brdf"].numel() * 4 + V * 4))
+    ops_texel = (CHAIN_OPS_PER_TEXEL if args.chain_rule
+                 else OPS_PER_TEXEL + (TRIPLE_EXTRA_OPS if args.triple else 0))
     achieved = texels * ops_texel / (ms_kernel * 1e-3) / 1e12
 
-    traffic = None
+    traffic = valu_util = None
     prof = os.path.join(ROOT, "profiles", f"relight_{w.name}_{args.form}_hbm.txt")
     if os.path.exists(prof):
         with open(prof) as fh:
             rec = json.load(fh)
         # counters were taken on the workload as configured, exact method
         if (rec.get("kernel_fingerprint") == kernel_fingerprint() and not args.chain_rule
-                and not args.nnz and not L):
+                and not args.nnz and not L and not args.triple):
             traffic = rec.get("hbm_bytes_per_launch")
+            valu_util = rec.get("valu_issue_util")
 
     line = {
         "metric": "relit vertices/s at rel-L2<=1e-3 vs FP64 oracle: plain FP32 vs BF16+MLP",
@@ -391,12 +413,18 @@ def main():
         **({"start_level": {"levels": L, "rotated_face": n_rot,
                             "note": "approximation; its error against the exact FP64 oracle "
                                     "is measured by tests/test_oracle_levels.py"}} if L else {}),
+        **({"triple_product": {"materials": args.triple,
+                               "note": "BRDF x cosine per material, visibility rows per "
+                                       "vertex; the tripling-coefficient sum evaluated as a "
+                                       "texel product before the transform"}}
+           if args.triple else {}),
         **({"chain_rule": {"note": "finest level rotated by the chain rule; an approximation "
                                    "whose error against the exact FP64 oracle is measured by "
                                    "tests/test_oracle_chain.py"}} if args.chain_rule else {}),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
-                     "traffic": traffic, "kernel": "relight_kernel",
+                     "traffic": traffic, "valu_issue_util": valu_util,
+                     "kernel": "relight_kernel",
                      "kernel_ms": round(ms_kernel, 4), "rotated_texels": texels,
                      "ops_per_texel": ops_texel,
                      "hbm_algorithmic_bytes": hbm_bytes,

@@ -85,7 +85,7 @@ typedef enum {
                                source's 2x2 blocks (Sec. V.A-V.B, eq:pde1 to
                                eq:pde3) instead of the exact resampling; the
                                coarser levels follow by the pyramid.  n >= 32
-                               only (else RRT_ERR_UNSUPPORTED). */
+                               and no brdf only (else RRT_ERR_UNSUPPORTED). */
 
 int rrt_abi_version(void);
 const char* rrt_status_string(int status);
@@ -158,6 +158,19 @@ typedef struct {
                             row cluster[v] (values stay per vertex);
                             out-of-range clusters contribute nothing */
   int nclusters;            /* C when cluster != NULL */
+  const float* brdf;        /* NULL (double product), or the triple product
+                               (Sec. III, eq:tripleSum): [M][6 n^2] float32
+                               texel-domain BRDF x cosine x solid angle in the
+                               local frame (16-byte aligned); the rotated
+                               lighting is multiplied by row material[v] texel
+                               by texel before the transform, which evaluates
+                               sum_ijk C_ijk a_i b_j c_k with a the rotated
+                               lighting, b the Haar coefficients of that row
+                               and c = the vertex's row (its visibility) */
+  const int32_t* material;  /* with brdf: NULL (row 0 for every vertex) or
+                               [V] row of each vertex; rows outside [0, M)
+                               give radiance 0 */
+  int nmaterials;           /* M >= 1 when brdf != NULL */
 } rrt_transport;
 
 typedef struct {

@@ -105,7 +105,7 @@ def haar_phase_shift(coef, rot):
 
 
 def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
-                 cluster=None):
+                 cluster=None, brdf=None, material=None):
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -120,7 +120,10 @@ def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, blo
                   _DTYPES[t_val.dtype],
                   _ptr_or_null(block_scale, "block_scale", torch.float32).value,
                   _ptr_or_null(cluster, "cluster", torch.int32).value,
-                  0 if cluster is None else t_idx.shape[0])
+                  0 if cluster is None else t_idx.shape[0],
+                  _ptr_or_null(brdf, "brdf", torch.float32).value,
+                  _ptr_or_null(material, "material", torch.int32).value,
+                  0 if brdf is None else brdf.shape[0])
     return L, R, T
 
 
@@ -138,7 +141,8 @@ def relight_workspace_bytes(n, light_idx, light_val, vert_rot, t_idx, t_val, fra
 
 
 def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
-            compensated=False, out=None, workspace=None, cluster=None, chain_rule=False):
+            compensated=False, out=None, workspace=None, cluster=None, chain_rule=False,
+            brdf=None, material=None):
     """radiance [F, V] float32.
 
     light_idx [k] int32, light_val [k] float32|float16; vert_rot [V, 3, 3]
@@ -148,9 +152,12 @@ def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, blo
     frame_rot [F, 3, 3] float32 or None.  With cluster [V] int32, t_idx is a
     per-cluster support table [C, nnz] and vertex v uses row cluster[v].
     chain_rule: rotate the finest level by the chain rule (n >= 32).
+    brdf [M, 6, n, n] float32 (texel-domain BRDF x cosine x solid angle in the
+    local frame) with material [V] int32 or None: the triple product, t_* then
+    hold the visibility rows.
     """
     L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
-                           cluster)
+                           cluster, brdf, material)
     flags = _flags(compensated, chain_rule)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
@@ -195,11 +202,11 @@ def prepare_lighting(n, light_idx, light_val, workspace=None, chain_rule=False):
 
 
 def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
-                     compensated=False, out=None, cluster=None):
+                     compensated=False, out=None, cluster=None, brdf=None, material=None):
     """relight() with a lighting already reconstructed by prepare_lighting()
     (the chain rule applies when the lighting was prepared for it)."""
     L, R, T = _descriptors(prep.n, prep.light_idx, prep.light_val, vert_rot, t_idx, t_val,
-                           frame_rot, block_scale, cluster)
+                           frame_rot, block_scale, cluster, brdf, material)
     if out is None:
         out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
     check(lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),

@@ -47,7 +47,8 @@ class Light(ctypes.Structure):
 class Transport(ctypes.Structure):
     _fields_ = [("nvert", c_int64), ("nnz", c_int), ("idx", c_void_p), ("val", c_void_p),
                 ("dtype", c_int), ("block_scale", c_void_p), ("cluster", c_void_p),
-                ("nclusters", c_int)]
+                ("nclusters", c_int), ("brdf", c_void_p), ("material", c_void_p),
+                ("nmaterials", c_int)]
 
 
 class Rotations(ctypes.Structure):

@@ -85,6 +85,12 @@ static int validate_relight(const rrt_light* L, const rrt_rotations* R, const rr
     return fail(RRT_ERR_INVALID, "relight: per-cluster supports need nclusters >= 1 and an idx table");
   if (int64_t(R->nframes) * T->nvert > (int64_t(1) << 40))
     return fail(RRT_ERR_INVALID, "relight: output too large");
+  if (T->brdf && T->nmaterials < 1)
+    return fail(RRT_ERR_INVALID, "relight: brdf needs nmaterials >= 1");
+  if (T->brdf && (reinterpret_cast<uintptr_t>(T->brdf) & 15u))
+    return fail(RRT_ERR_INVALID, "relight: brdf not 16-byte aligned");
+  if (T->brdf && int64_t(T->nmaterials) * cells > (int64_t(1) << 40))
+    return fail(RRT_ERR_INVALID, "relight: brdf table too large");
   return RRT_OK;
 }
 
@@ -205,11 +211,14 @@ int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_
   return RRT_OK;
 }
 
-static int check_relight_flags(const rrt_light* L, unsigned flags) {
+static int check_relight_flags(const rrt_light* L, unsigned flags,
+                               const rrt_transport* T = nullptr) {
   if (flags & ~(RRT_COMPENSATED | RRT_CHAIN_RULE))
     return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
   if ((flags & RRT_CHAIN_RULE) && L->n < 32)
     return fail(RRT_ERR_UNSUPPORTED, "relight: chain rule needs n >= 32 (n=%d)", L->n);
+  if ((flags & RRT_CHAIN_RULE) && T && T->brdf)
+    return fail(RRT_ERR_UNSUPPORTED, "relight: chain rule with a brdf (triple product)");
   return RRT_OK;
 }
 
@@ -241,7 +250,7 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
                          void* stream) {
   int st = validate_relight(L, R, T);
   if (st) return st;
-  st = check_relight_flags(L, flags);
+  st = check_relight_flags(L, flags, T);
   if (st) return st;
   const bool f16 = L->dtype == RRT_F16;
   const RelightWs w = relight_ws(L->n, f16);
@@ -267,6 +276,9 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
   a.flags = flags;
   a.out = radiance;
   a.blocks = static_cast<const char*>(ws) + w.dense_off;
+  a.brdf = T->brdf;
+  a.material = T->brdf ? T->material : nullptr;
+  a.nmaterials = T->brdf ? T->nmaterials : 0;
   return launch_relight(a, static_cast<hipStream_t>(stream));
 }
 
@@ -275,7 +287,7 @@ int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport*
   // validate everything before enqueueing anything
   int st = validate_relight(L, R, T);
   if (st) return st;
-  st = check_relight_flags(L, flags);
+  st = check_relight_flags(L, flags, T);
   if (st) return st;
   st = check_ws(ws, ws_bytes, relight_ws(L->n, L->dtype == RRT_F16).total, "relight");
   if (st) return st;

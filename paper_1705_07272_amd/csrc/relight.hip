@@ -177,6 +177,9 @@ struct RelightParams {
   int listed;       // entries of each row listed in LDS: min(nnz, kMaxListed)
   int group_faces;  // faces whose block sums fit in LDS together
   const float4* blocks;  // chain rule: (S, H, V, D) of every 2x2 source block
+  const float* brdf;        // triple product: [nmat][6 n^2] texel factor, or NULL
+  const int32_t* material;  // [V] row of brdf, or NULL (row 0)
+  int nmat;
 };
 
 // Unscaled 2x2 levels with block side 2..T inside a thread's T x T tile, in
@@ -318,8 +321,9 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
 
 // Q: block side (min(n, kBlock)); the wave's TS x TS lanes each own a T x T tile.
 // CHAIN: the finest level comes from the chain rule on the source blocks
-// (Q = 32 only) instead of the exact resampling.
-template <int Q, typename SrcT, bool CHAIN>
+// (Q = 32 only) instead of the exact resampling.  BRDF: triple product, the
+// rotated texels are multiplied by the vertex's BRDF factor (not with CHAIN).
+template <int Q, typename SrcT, bool CHAIN, bool BRDF>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
   constexpr int T = Q / TS;           // texels per tile side
@@ -357,6 +361,15 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
     } else {
       idx_row = p.tidx + v * p.nnz;
     }
+  }
+  // triple product: this vertex's BRDF factor (its material's row)
+  const float* brdf_row = nullptr;
+  if (BRDF) {
+    const int mat = p.material ? p.material[v] : 0;
+    if (mat >= 0 && mat < p.nmat)
+      brdf_row = p.brdf + int64_t(mat) * 6 * (n << logn);
+    else
+      row_valid = false;
   }
   const int nnz = row_valid ? p.nnz : 0;
   const int listed = row_valid ? p.listed : 0;
@@ -514,6 +527,26 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
 #pragma unroll
                 for (int cc = 0; cc < T; ++cc)
                   g[rr][cc] = img[(ty * T + rr) * STRIDE + tx * T + cc];
+              if constexpr (BRDF) {
+                {
+                  // triple product: times the BRDF factor at each destination texel
+                  const float* br =
+                      brdf_row + ((face * n + by * Q + ty * T) << logn) + bx * Q + tx * T;
+#pragma unroll
+                  for (int rr = 0; rr < T; ++rr) {
+                    if constexpr (T == 4) {
+                      const float4 f4 = *reinterpret_cast<const float4*>(br + (rr << logn));
+                      g[rr][0] *= f4.x;
+                      g[rr][1] *= f4.y;
+                      g[rr][2] *= f4.z;
+                      g[rr][3] *= f4.w;
+                    } else {
+#pragma unroll
+                      for (int cc = 0; cc < T; ++cc) g[rr][cc] *= br[(rr << logn) + cc];
+                    }
+                  }
+                }
+              }
               if constexpr (CHAIN) {
                 tile_levels_from<T, 4>(g);
               } else {
@@ -689,26 +722,32 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   dst[int64_t(r) * 6 * per_face + q] = src[min(at, unsigned(6 * per_face - 1))];
 }
 
-template <int Q, typename SrcT, bool CHAIN = false>
+template <int Q, typename SrcT, bool CHAIN = false, bool BRDF = false>
 int launch_q(const RelightParams& prm, int64_t nvert, hipStream_t s) {
   const int G = (1 << prm.logn) / Q;
   const size_t lds = ((size_t(Q) * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) & ~size_t(7)) +
                      size_t(prm.group_faces) * G * G * 8;
-  hipLaunchKernelGGL((relight_kernel<Q, SrcT, CHAIN>), dim3(unsigned(nvert)), dim3(kThreads), lds,
-                     s, prm);
+  hipLaunchKernelGGL((relight_kernel<Q, SrcT, CHAIN, BRDF>), dim3(unsigned(nvert)),
+                     dim3(kThreads), lds, s, prm);
   return check_launch("relight_kernel");
+}
+
+template <typename SrcT, bool BRDF>
+int launch_size(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
+  switch (n < kBlock ? n : kBlock) {
+    case 2: return launch_q<2, SrcT, false, BRDF>(prm, nvert, s);
+    case 4: return launch_q<4, SrcT, false, BRDF>(prm, nvert, s);
+    case 8: return launch_q<8, SrcT, false, BRDF>(prm, nvert, s);
+    case 16: return launch_q<16, SrcT, false, BRDF>(prm, nvert, s);
+    default: return launch_q<kBlock, SrcT, false, BRDF>(prm, nvert, s);
+  }
 }
 
 template <typename SrcT>
 int launch_src(const RelightParams& prm, int n, int64_t nvert, bool chain, hipStream_t s) {
   if (chain) return launch_q<kBlock, SrcT, true>(prm, nvert, s);
-  switch (n < kBlock ? n : kBlock) {
-    case 2: return launch_q<2, SrcT>(prm, nvert, s);
-    case 4: return launch_q<4, SrcT>(prm, nvert, s);
-    case 8: return launch_q<8, SrcT>(prm, nvert, s);
-    case 16: return launch_q<16, SrcT>(prm, nvert, s);
-    default: return launch_q<kBlock, SrcT>(prm, nvert, s);
-  }
+  return prm.brdf ? launch_size<SrcT, true>(prm, n, nvert, s)
+                  : launch_size<SrcT, false>(prm, n, nvert, s);
 }
 
 }  // namespace
@@ -736,6 +775,9 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   const int fit = kGroupBytes / (G * G * 8);
   p.group_faces = fit < 1 ? 1 : (fit > 6 ? 6 : fit);
   p.blocks = static_cast<const float4*>(a.blocks);
+  p.brdf = a.brdf;
+  p.material = a.material;
+  p.nmat = a.nmaterials;
   const bool chain = (a.flags & RRT_CHAIN_RULE) != 0;
   return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, chain, s)
                    : launch_src<float>(p, a.n, a.nvert, chain, s);

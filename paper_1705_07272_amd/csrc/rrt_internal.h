@@ -60,6 +60,9 @@ struct RelightLaunch {
   unsigned flags;
   float* out;               // [F][V]
   const void* blocks;       // chain rule: float4 (S, H, V, D) per 2x2 source block
+  const float* brdf;        // triple product: [M][6 n^2] texel factor, or NULL
+  const int32_t* material;  // [V] row of brdf, or NULL (row 0)
+  int nmaterials;
 };
 int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStream_t s);
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,

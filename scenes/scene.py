@@ -29,6 +29,7 @@ STREAM_FRAME = 3
 STREAM_EXP = 4
 STREAM_VIS = 5
 STREAM_MESH = 6
+STREAM_MATERIAL = 7
 
 # Faces as signed axis permutations: direction = A_F @ (U, V, N).
 FACE_AXES = np.array([
@@ -213,6 +214,25 @@ def phong_lobe(n_exp, cos_y, omega):
     return (n_exp + 2.0) / (2.0 * np.pi) * np.power(c[None], n_exp + 1.0) * omega[None, None]
 
 
+def material_exponents(w: Workload, count):
+    """Phong exponents of `count` materials, uniform in [exp_lo, exp_hi]."""
+    return rng(w.cfg, STREAM_MATERIAL).uniform(w.exp_lo, w.exp_hi, size=count)
+
+
+def material_ids(w: Workload, count):
+    """Material of every vertex, uniform over `count` materials (int32 [V])."""
+    return rng(w.cfg, STREAM_MATERIAL, 1).integers(0, count, size=w.nverts).astype(np.int32)
+
+
+def brdf_pixels(w: Workload, count):
+    """Texel-domain BRDF x cosine x solid angle of each material in the local
+    frame, [count, 6, n, n] float64: the Phong lobe of transport_pixels
+    without the visibility."""
+    n = w.n
+    return phong_lobe(material_exponents(w, count), texel_directions(n)[..., 1],
+                      texel_solid_angles(n))
+
+
 def transport_pixels(w: Workload, exps, vertex_ids):
     """Pixel-domain transport [B, 6, n, n] float64 for the given vertices."""
     n = w.n
@@ -233,9 +253,16 @@ def transport_pixels_torch(w: Workload, exps, vertex_ids, device, dtype=None):
     omega = torch.as_tensor(texel_solid_angles(n), device=device)
     e = torch.as_tensor(np.asarray(exps, dtype=np.float64), device=device).view(-1, 1, 1, 1)
     lobe = (e + 2.0) / (2.0 * np.pi) * torch.pow(cos_y.clamp_min(0.0)[None], e + 1.0) * omega[None, None]
+    return (lobe * visibility_torch(w, vertex_ids, device)).to(dtype)
+
+
+def visibility_torch(w: Workload, vertex_ids, device):
+    """visibility_np(w.cfg, vertex_ids, w.n, w.occlusion) evaluated with torch
+    on `device` (bool [B, 6, n, n])."""
+    import torch
+    n = w.n
     vid = torch.as_tensor(np.asarray(vertex_ids, dtype=np.int64), device=device).view(-1, 1)
     tex = torch.arange(6 * n * n, device=device, dtype=torch.int64).view(1, -1)
     zero = torch.zeros((), dtype=torch.int64, device=device)
     r0, _, _, _ = philox4x32_torch(tex, vid, zero + STREAM_VIS, zero, SEED, w.cfg)
-    vis = (r0 >= occlusion_threshold(w.occlusion)).view(-1, 6, n, n)
-    return (lobe * vis).to(dtype)
+    return (r0 >= occlusion_threshold(w.occlusion)).view(-1, 6, n, n)

@@ -62,3 +62,24 @@ def frame_errors(got, ref):
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
     return [rel_l2(got[f], ref[f]) for f in range(ref.shape[0])]
+
+
+def triple_case(w, materials, vertex_ids=None, batch=64):
+    """Stored inputs of the triple product: the lighting and rotations of
+    build_case, the materials' texel-domain BRDF factors [M, 6, n, n]
+    (float32), each vertex's material, and its visibility rows (Haar
+    coefficients of the binary visibility, top-nnz by the checker)."""
+    from scenes.scene import brdf_pixels, material_ids, visibility_np
+    vertex_ids = np.arange(w.nverts) if vertex_ids is None else np.asarray(vertex_ids)
+    pix = lighting_pixels(w.cfg, w.n)
+    li, lv = lighting_coefficients(pix, w.k_light)
+    idx_parts, val_parts = [], []
+    for s in range(0, len(vertex_ids), batch):
+        vis = visibility_np(w.cfg, vertex_ids[s:s + batch], w.n, w.occlusion).astype(np.float64)
+        i, v = transport_rows(vis, w.nnz)
+        idx_parts.append(i)
+        val_parts.append(v)
+    return dict(n=w.n, light_idx=li, light_val=lv, vert_rot=vertex_rotations(w)[vertex_ids],
+                frame_rot=frame_rotations(w), brdf=brdf_pixels(w, materials).astype(np.float32),
+                material=material_ids(w, materials)[vertex_ids],
+                t_idx=np.concatenate(idx_parts), t_val=np.concatenate(val_parts))

@@ -208,3 +208,27 @@ def test_coarsen_validation(rrt):
     assert lib.rrt_coarsen_indices(_p(0), 10, 16, 2, _p(8), None) == E.RRT_ERR_INVALID   # null
     assert lib.rrt_coarsen_indices(_p(0), 0, 16, 3, _p(0), None) == E.RRT_OK             # empty
 
+
+
+def test_triple_product_validation(rrt):
+    """A BRDF table needs nmaterials >= 1 and 16-byte alignment; the chain
+    rule refuses it.  Checked before anything is enqueued."""
+    E = rrt._abi
+    lib = rrt.lib
+
+    def desc(n=32, brdf=256, nmat=2):
+        L = E.Light(n, 10, 8, 8, 0)
+        R = E.Rotations(1, 0, 8)
+        T = E.Transport(5, 16, 8, 8, 0, 0, 0, 0, brdf, 0, nmat)
+        return L, R, T
+
+    assert _relight_ws(rrt, *desc())[0] == E.RRT_OK
+    assert _relight_ws(rrt, *desc(nmat=0))[0] == E.RRT_ERR_INVALID
+    assert _relight_ws(rrt, *desc(brdf=264))[0] == E.RRT_ERR_INVALID
+    assert _relight_ws(rrt, *desc(brdf=0, nmat=0))[0] == E.RRT_OK
+    L, R, T = desc()
+    assert lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8),
+                           E.RRT_CHAIN_RULE, _p(256), 1 << 30, None) == E.RRT_ERR_UNSUPPORTED
+    assert lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8),
+                                    E.RRT_CHAIN_RULE, _p(256), 1 << 30,
+                                    None) == E.RRT_ERR_UNSUPPORTED

@@ -147,3 +147,39 @@ def test_full_cube128_v50000_f64frames_e4m3_f16(rrt, frames_case):
     the block scale: |err| <= (2^-4 + 2^-8) sum_k |T_k ghat_k|."""
     _, rel = _frames_run(rrt, frames_case, "e4m3")
     assert rel <= 2.0 ** -4 + 2.0 ** -8
+
+
+def test_full_cube128_v50000_triple_product(rrt):
+    """The benchmark scene as a triple product (8 Phong materials, visibility
+    rows top-256 per vertex) in the launch the bench times: sampled outputs
+    against the checker's tripling-coefficient sum, rel-L2 <= 1e-5."""
+    from cases import frame_errors, triple_case
+    from oracle.triple import relight_triple
+    from scenes.scene import WORKLOADS, visibility_torch
+    w = WORKLOADS[2]
+    M = 8
+    sample = _sample(w.nverts, 24, 3)
+    case = triple_case(w, M, sample)
+    idx = torch.empty((w.nverts, w.nnz), dtype=torch.int32, device="cuda")
+    val = torch.empty((w.nverts, w.nnz), dtype=torch.float32, device="cuda")
+    for s in range(0, w.nverts, 2048):
+        e = min(w.nverts, s + 2048)
+        i, v = rrt.project_rows(visibility_torch(w, np.arange(s, e), "cuda").float().contiguous(),
+                                w.nnz)
+        idx[s:e] = i
+        val[s:e] = v
+    sel = torch.from_numpy(sample).cuda().long()
+    idx[sel] = torch.from_numpy(case["t_idx"]).cuda()
+    val[sel] = torch.from_numpy(case["t_val"]).cuda()
+    from scenes.scene import material_ids, vertex_rotations
+    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
+                      torch.from_numpy(case["light_val"]).cuda(),
+                      torch.from_numpy(vertex_rotations(w)).cuda(), idx, val,
+                      brdf=torch.from_numpy(case["brdf"]).cuda(),
+                      material=torch.from_numpy(material_ids(w, M)).cuda())
+    torch.cuda.synchronize()
+    ref = relight_triple(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
+                         case["t_idx"], case["t_val"], case["brdf"], case["material"])
+    err = max(frame_errors(out.cpu().numpy()[:, sample], ref))
+    print(f"cube128 V=50000 triple product, 8 materials: sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5

@@ -428,3 +428,54 @@ def test_relight_chain_rule_prepared_and_cube_rotations(rrt):
     two = rrt.relight_prepared(prep, dev(case["vert_rot"]), dev(case["t_idx"]), dev(case["t_val"]))
     torch.cuda.synchronize()
     assert np.array_equal(one, two.cpu().numpy())
+
+
+# ---------------------------------------------------------------- triple product (f2)
+def run_triple(rrt, case, **kw):
+    out = rrt.relight(case["n"], dev(case["light_idx"]), dev(case["light_val"]),
+                      dev(case["vert_rot"]), dev(case["t_idx"]), dev(case["t_val"]),
+                      frame_rot=None if case["frame_rot"] is None else dev(case["frame_rot"]),
+                      brdf=dev(case["brdf"]), material=dev(case["material"]), **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,V,nnz,M,frames", [(2, 7, 24, 2, 1), (4, 9, 40, 2, 1),
+                                              (16, 21, 128, 3, 1), (32, 37, 256, 4, 2),
+                                              (64, 23, 256, 8, 1), (128, 17, 256, 8, 1)])
+def test_relight_triple_product(rrt, n, V, nnz, M, frames):
+    """BRDF and visibility kept separate: the device's texel-domain product
+    against the checker's literal tripling-coefficient sum on the same stored
+    inputs (materials, visibility rows, lighting)."""
+    from cases import triple_case, workload
+    from oracle.triple import relight_triple
+    w = workload(700 + n, n, min(1024, 6 * n * n), V, nnz, nframes=frames)
+    case = triple_case(w, M)
+    ref = relight_triple(case["light_idx"], case["light_val"], n, case["vert_rot"],
+                         case["frame_rot"], case["t_idx"], case["t_val"], case["brdf"],
+                         case["material"], return_scale=True)
+    check_frames(run_triple(rrt, case, compensated=(n == 32)), ref, rel_l2=n >= 32)
+
+
+def test_relight_triple_edge_cases(rrt):
+    """Materials outside [0, M) give exactly 0; a BRDF of ones gives the
+    double product bit for bit; no material table means row 0; the chain
+    rule refuses a BRDF."""
+    from cases import triple_case, workload
+    n = 32
+    case = triple_case(workload(760, n, 1024, 12, 256), 3)
+    mat = case["material"].copy()
+    mat[[1, 5, 9]] = [-1, 3, 1 << 30]
+    got = run_triple(rrt, dict(case, material=mat))
+    assert np.all(got[0, [1, 5, 9]] == 0.0) and np.all(got[0, [0, 2, 3]] != 0.0)
+    ones = dict(case, brdf=np.ones((2, 6, n, n), np.float32), material=np.zeros(12, np.int32))
+    plain = run_relight(rrt, dict(case, t_idx=case["t_idx"], t_val=case["t_val"]))
+    assert np.array_equal(run_triple(rrt, ones), plain)
+    r0 = rrt.relight(n, dev(case["light_idx"]), dev(case["light_val"]), dev(case["vert_rot"]),
+                     dev(case["t_idx"]), dev(case["t_val"]), brdf=dev(case["brdf"]))
+    both = run_triple(rrt, dict(case, material=np.zeros(12, np.int32)))
+    assert np.array_equal(r0.cpu().numpy(), both)
+    with pytest.raises(RuntimeError):
+        rrt.relight(n, dev(case["light_idx"]), dev(case["light_val"]), dev(case["vert_rot"]),
+                    dev(case["t_idx"]), dev(case["t_val"]), brdf=dev(case["brdf"]),
+                    material=dev(case["material"]), chain_rule=True)
