@@ -34,6 +34,12 @@ OPS_PER_TEXEL = 27
 CHAIN_OPS_PER_TEXEL = 21
 # The triple product adds the read of the BRDF factor and the product.
 TRIPLE_EXTRA_OPS = 2
+# Longitude-latitude rule per texel: the centre's sines and cosines (4
+# reads, 2 products), the elevation rotation (6), rho (4), column select,
+# shifts, flat index, gather and the levels' share (16), plus per level of
+# the two binary searches 7 (two reads, two compares, two adds, one product).
+LATLONG_OPS_BASE = 30
+LATLONG_OPS_PER_LEVEL = 7
 
 KERNEL_SOURCES = ["paper_1705_07272_amd/csrc/relight.hip", "paper_1705_07272_amd/csrc/geometry.h"]
 
@@ -145,6 +151,84 @@ def device_inputs(w, form, batch=2048, materials=0):
     torch.cuda.synchronize()
     return dict(pix=pix, rot=rot, frot=frot, idx=idx, val=val, scale=scale, brdf=brdf,
                 material=mat)
+
+
+def run_latlong(args):
+    """Longitude-latitude map (Sec. V.A): the timed step is the lighting's
+    Haar transform and top-k, then rrt_relight_latlong (reconstruction,
+    tables, relight of every vertex under its elevation rotation and
+    azimuth shifts)."""
+    import numpy as np
+    import torch
+
+    import paper_1705_07272_amd as rrt
+    from scenes.latlong import (LATLONG_WORKLOADS, lighting_pixels, phong_exponents, rotations,
+                                transport_pixels_torch)
+    w = LATLONG_WORKLOADS[args.latlong]
+    dev = torch.device("cuda")
+    H, V = w.H, w.nverts
+    pix = torch.from_numpy(lighting_pixels(w.cfg, H)).to(dev)
+    elev, shift = rotations(w)
+    elev, shift = torch.from_numpy(elev).to(dev), torch.from_numpy(shift).to(dev)
+    exps = phong_exponents(w)
+    idx = torch.empty((V, w.nnz), dtype=torch.int32, device=dev)
+    val = torch.empty((V, w.nnz), dtype=torch.float32, device=dev)
+    for s in range(0, V, 2048):
+        e = min(V, s + 2048)
+        T = transport_pixels_torch(w, exps[s:e], np.arange(s, e), dev, dtype=torch.float32)
+        idx[s:e], val[s:e] = rrt.project_rows(T.contiguous(), w.nnz)
+    out = torch.empty(V, dtype=torch.float32, device=dev)
+    ws = torch.empty(2 * 2 * H * H * 4 + 7 * H * 4 + 1024, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    print("inputs ready", file=sys.stderr, flush=True)
+
+    def step(ev=None):
+        coef = rrt.haar_forward(pix)
+        li, lv = rrt.topk(coef.view(1, -1), w.k_light)
+        if ev is not None:
+            ev[0].record()
+        rrt.relight_latlong(H, li[0], lv[0], elev, shift, idx, val, out=out, workspace=ws)
+        if ev is not None:
+            ev[1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for k in range(args.steps):
+        step(evs[k])
+    t1.record()
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    ms_kernel = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    faces = torch.zeros((V, 3), dtype=torch.float32, device=dev)
+    fid = idx.long() // (H * H)
+    faces.scatter_(1, torch.where(idx >= 0, fid, torch.full_like(fid, 2)), 1.0)
+    texels = int((faces[:, :2] > 0).sum().item()) * H * H
+    ops = LATLONG_OPS_BASE + LATLONG_OPS_PER_LEVEL * int(np.log2(H))
+    achieved = texels * ops / (ms_kernel * 1e-3) / 1e12
+    hbm = V * w.nnz * 8 + V * 16 + V * 4
+    print(json.dumps({
+        "metric": "relit vertices/s at rel-L2<=1e-3 vs FP64 oracle: plain FP32 vs BF16+MLP",
+        "value": round(V / (ms_step * 1e-3), 1), "unit": "relit vertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "map": f"latlong {H}x{2 * H}", "light_coeffs": w.k_light,
+                   "vertices": V, "frames": 1, "transport_nnz": w.nnz, "form": "f32"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_ALU_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_ALU_TOPS, 4), "traffic": None,
+                     "kernel": "rrt_relight_latlong (reconstruction + tables + relight_kernel)",
+                     "kernel_ms": round(ms_kernel, 4), "rotated_texels": texels,
+                     "ops_per_texel": ops, "hbm_algorithmic_bytes": hbm,
+                     "hbm_achieved_gbs": round(hbm / (ms_kernel * 1e-3) / 1e9, 1),
+                     "hbm_peak_gbs": PEAK_HBM_GBS},
+        "cpu_baseline": None}), flush=True)
 
 
 def run_learned(args, w):
@@ -271,6 +355,9 @@ def main():
     ap.add_argument("--nnz", type=int, default=0,
                     help="transport coefficients kept per vertex (budget sweep; 0 = the "
                          "workload's own)")
+    ap.add_argument("--latlong", type=int, default=0, metavar="CFG",
+                    help="longitude-latitude map workload (6: 128x256, 7: 256x512), "
+                         "Sec. V.A elevation rotation plus azimuth shifts")
     ap.add_argument("--triple", type=int, default=0, metavar="M",
                     help="triple product with M materials: BRDF factors per material, the "
                          "rows hold each vertex's visibility (Sec. III)")
@@ -299,7 +386,7 @@ def main():
     base = None
     # the oracle baseline is of the workload as configured (no budget override)
     if (not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp"
-            and not args.nnz and not args.triple):
+            and not args.nnz and not args.triple and not args.latlong):
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
         base = cpu_baseline(args.workload, args.cpu_sample, workers)
         print(f"cpu baseline done: {base['sample']}", file=sys.stderr, flush=True)
@@ -320,6 +407,9 @@ def main():
 
     if args.form == "mlp":
         run_learned(args, WORKLOADS[4] if args.workload == 2 else w)
+        return
+    if args.latlong:
+        run_latlong(args)
         return
 
     inp = device_inputs(w, args.form, materials=args.triple)

@@ -92,15 +92,17 @@ const char* rrt_status_string(int status);
 const char* rrt_last_error(void);
 
 /* ------------------------------------------------------------------------
- * Haar transform of cube maps (representation, Sec. III / Sec. V.B).
- *   pix, coef: [count][6][n][n] float32, may not overlap.
- *   count >= 0 (0 = no-op), 1 <= n <= 1024, n a power of two.
+ * Haar transform of square maps (representation, Sec. III / Sec. V.B):
+ * every n x n square is transformed on its own (a cube map is 6 squares,
+ * one per face; a longitude-latitude map 2).
+ *   pix, coef: [squares][n][n] float32, may not overlap.
+ *   squares >= 0 (0 = no-op), 1 <= n <= 1024, n a power of two.
  *   No workspace: for n > 128 the work is split into 128 x 128 tiles plus
  *   one coarse pass, and the tile sums between the two launches are staged
  *   in the output buffer itself.
  * --------------------------------------------------------------------- */
-int rrt_haar_forward(const float* pix, float* coef, int n, int64_t count, void* stream);
-int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t count, void* stream);
+int rrt_haar_forward(const float* pix, float* coef, int n, int64_t squares, void* stream);
+int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t squares, void* stream);
 
 /* ------------------------------------------------------------------------
  * Non-linear approximation (Sec. III, Haar-domain methods): keep the k
@@ -210,6 +212,40 @@ int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_
 int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
                          float* radiance, unsigned flags, const void* ws, size_t ws_bytes,
                          void* stream);
+
+/* ------------------------------------------------------------------------
+ * Relighting on the longitude-latitude map (Sec. V.A; the elevation rotation
+ * plus azimuth shift of its last paragraphs).  The map has H rows (elevation
+ * t from +Y) and W = 2H columns (azimuth f), texel (i, j) spans
+ * [i, i+1) x [j, j+1) in units of pi/H; it is stored as two H x H squares,
+ * square s holding columns s H .. s H + H - 1, each with its own Haar
+ * transform, so L->idx and T->idx index [2][H][H] (L->n = H).
+ * Vertex v's rotation is R_v = R_y(s_a pi/H) R_x(b) R_y(s_c pi/H) (R_y
+ * adds to the azimuth; R_x = [[1,0,0],[0,cos b,-sin b],[0,sin b,cos b]]):
+ *   radiance[v] = sum_k T_v[k] (W g_v)[k],  g_v(i, j) = P(source(i, j)),
+ * P = W^T L, and source(i, j) the texel of R_x(b) p(i, j + s_c) shifted by
+ * s_a columns, p = (sin t sin f, cos t, sin t cos f) at the texel centre.
+ * The texel of R_x(b) p is decided in binary32 by one fixed sequence of
+ * rounded operations: p from binary32 sines and cosines of the centres,
+ * q_y = cb p_y - sb p_z, q_z = sb p_y + cb p_z, rho = sqrt(q_x^2 + q_z^2),
+ * row = #{0 < k < H : q_y <= C_k}, c = #{0 < k < H : q_z <= C_k rho} with
+ * C_k = binary32 cos(k pi / H), column = c if q_x >= 0 else W - 1 - c.
+ *   H: power of two in [4, 512]; transport as rrt_transport without
+ *   cluster or brdf; flags: RRT_COMPENSATED only; radiance [V] float32.
+ *   Workspace: rrt_relight_latlong_workspace() bytes, 256-byte aligned:
+ *   [2 H^2 float32 staging][source map 2 H^2 float32|binary16][7 H float32
+ *   tables: sin, cos of the row centres (H each), sin, cos of the column
+ *   centres (2H each), C_k (H)], each part starting 256-byte aligned.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  const float* elev;     /* [V][2] (cos b, sin b) of R_x(b), binary32 */
+  const int32_t* shift;  /* [V][2] (s_a, s_c) in columns, any integers (mod 2H) */
+} rrt_latlong_rotations;
+
+int rrt_relight_latlong_workspace(const rrt_light* L, size_t* bytes);
+int rrt_relight_latlong(const rrt_light* L, const rrt_latlong_rotations* R,
+                        const rrt_transport* T, float* radiance, unsigned flags, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Storage conversion of coefficient values (reduced-precision forms).

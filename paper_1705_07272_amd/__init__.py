@@ -11,9 +11,10 @@ import torch
 
 from . import _abi
 from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
-                   RRT_S16, Light, RrtError, Rotations, Transport, check, lib)
+                   RRT_S16, LatLongRotations, Light, RrtError, Rotations, Transport, check, lib)
 
-__all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight", "mlp_encode",
+__all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight",
+           "relight_latlong", "mlp_encode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
@@ -50,9 +51,10 @@ def _workspace(nbytes, device):
 
 
 def haar_forward(pix, out=None):
-    """Per-face Haar transform of cube maps [..., 6, n, n] (float32)."""
+    """Haar transform of every n x n square of [..., n, n] float32 (cube maps
+    [..., 6, n, n], lat-long maps [..., 2, H, H])."""
     n = pix.shape[-1]
-    count = pix.numel() // (6 * n * n) if pix.numel() else 0
+    count = pix.numel() // (n * n) if pix.numel() else 0
     out = torch.empty_like(pix) if out is None else out
     check(lib.rrt_haar_forward(_dev(pix, "pix", torch.float32), _dev(out, "out", torch.float32),
                                n, count, _stream()))
@@ -61,7 +63,7 @@ def haar_forward(pix, out=None):
 
 def haar_inverse(coef, out=None):
     n = coef.shape[-1]
-    count = coef.numel() // (6 * n * n) if coef.numel() else 0
+    count = coef.numel() // (n * n) if coef.numel() else 0
     out = torch.empty_like(coef) if out is None else out
     check(lib.rrt_haar_inverse(_dev(coef, "coef", torch.float32), _dev(out, "out", torch.float32),
                                n, count, _stream()))
@@ -214,6 +216,38 @@ def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=N
                                    _flags(compensated, prep.chain_rule),
                                    _dev(prep.workspace, "workspace"), prep.workspace.numel(),
                                    _stream()))
+    return out
+
+
+def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_scale=None,
+                    compensated=False, out=None, workspace=None):
+    """radiance [V] float32 on the longitude-latitude map (rrt_relight_latlong).
+
+    light_idx [k] int32 / light_val [k] float32|float16 over [2, H, H];
+    elev [V, 2] float32 (cos b, sin b); shift [V, 2] int32 (s_a, s_c);
+    t_idx [V, nnz] int32 or None (dense), t_val [V, nnz] as for relight()."""
+    L = Light(H, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
+              _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
+              _DTYPES[light_val.dtype])
+    R = LatLongRotations(_dev(elev, "elev", torch.float32).value,
+                         _dev(shift, "shift", torch.int32).value)
+    nvert = elev.shape[0]
+    nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
+    T = Transport(nvert, nnz, _ptr_or_null(t_idx, "transport_idx", torch.int32).value,
+                  _dev(t_val, "transport_val",
+                       (torch.float32, torch.bfloat16, torch.uint8, torch.int16)).value,
+                  _DTYPES[t_val.dtype], _ptr_or_null(block_scale, "block_scale", torch.float32).value,
+                  None, 0, None, None, 0)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_latlong_workspace(ctypes.byref(L), ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _workspace(nbytes.value, elev.device)
+    if out is None:
+        out = torch.empty(nvert, dtype=torch.float32, device=elev.device)
+    check(lib.rrt_relight_latlong(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
+                                  _dev(out, "out", torch.float32),
+                                  RRT_COMPENSATED if compensated else 0,
+                                  _dev(workspace, "workspace"), workspace.numel(), _stream()))
     return out
 
 

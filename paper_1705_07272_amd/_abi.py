@@ -55,6 +55,10 @@ class Rotations(ctypes.Structure):
     _fields_ = [("nframes", c_int), ("frame_rot", c_void_p), ("vert_rot", c_void_p)]
 
 
+class LatLongRotations(ctypes.Structure):
+    _fields_ = [("elev", c_void_p), ("shift", c_void_p)]
+
+
 P = ctypes.POINTER
 
 SIGNATURES = {
@@ -75,6 +79,9 @@ SIGNATURES = {
     "rrt_relight": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint, c_void_p,
                             c_size_t, c_void_p]),
     "rrt_relight_prepare": (c_int, [P(Light), c_uint, c_void_p, c_size_t, c_void_p]),
+    "rrt_relight_latlong_workspace": (c_int, [P(Light), P(c_size_t)]),
+    "rrt_relight_latlong": (c_int, [P(Light), P(LatLongRotations), P(Transport), c_void_p, c_uint,
+                                    c_void_p, c_size_t, c_void_p]),
     "rrt_relight_prepared": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint,
                                      c_void_p, c_size_t, c_void_p]),
     "rrt_convert": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p]),

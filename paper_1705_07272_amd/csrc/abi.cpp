@@ -115,26 +115,26 @@ const char* rrt_status_string(int status) {
 
 const char* rrt_last_error(void) { return g_last_error; }
 
-int rrt_haar_forward(const float* pix, float* coef, int n, int64_t count, void* stream) {
+int rrt_haar_forward(const float* pix, float* coef, int n, int64_t squares, void* stream) {
   if (!valid_n(n, 1)) return fail(RRT_ERR_INVALID, "haar_forward: n=%d not a power of two in [1,1024]", n);
-  if (count < 0) return fail(RRT_ERR_INVALID, "haar_forward: count=%lld < 0", (long long)count);
-  if (count == 0) return RRT_OK;
+  if (squares < 0) return fail(RRT_ERR_INVALID, "haar_forward: squares=%lld < 0", (long long)squares);
+  if (squares == 0) return RRT_OK;
   if (!pix || !coef) return fail(RRT_ERR_INVALID, "haar_forward: null pointer");
   if (pix == coef) return fail(RRT_ERR_INVALID, "haar_forward: in-place transform not supported");
-  if (count * 6 * (n / (n < 128 ? n : 128)) * (n / (n < 128 ? n : 128)) > int64_t(0x7fffffff))
-    return fail(RRT_ERR_INVALID, "haar_forward: count too large");
-  return launch_haar_forward(pix, coef, n, count, static_cast<hipStream_t>(stream));
+  if (squares * (n / (n < 128 ? n : 128)) * (n / (n < 128 ? n : 128)) > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "haar_forward: too many squares");
+  return launch_haar_forward(pix, coef, n, squares, static_cast<hipStream_t>(stream));
 }
 
-int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t count, void* stream) {
+int rrt_haar_inverse(const float* coef, float* pix, int n, int64_t squares, void* stream) {
   if (!valid_n(n, 1)) return fail(RRT_ERR_INVALID, "haar_inverse: n=%d not a power of two in [1,1024]", n);
-  if (count < 0) return fail(RRT_ERR_INVALID, "haar_inverse: count=%lld < 0", (long long)count);
-  if (count == 0) return RRT_OK;
+  if (squares < 0) return fail(RRT_ERR_INVALID, "haar_inverse: squares=%lld < 0", (long long)squares);
+  if (squares == 0) return RRT_OK;
   if (!pix || !coef) return fail(RRT_ERR_INVALID, "haar_inverse: null pointer");
   if (pix == coef) return fail(RRT_ERR_INVALID, "haar_inverse: in-place transform not supported");
-  if (count * 6 * (n / (n < 128 ? n : 128)) * (n / (n < 128 ? n : 128)) > int64_t(0x7fffffff))
-    return fail(RRT_ERR_INVALID, "haar_inverse: count too large");
-  return launch_haar_inverse(coef, pix, n, count, static_cast<hipStream_t>(stream));
+  if (squares * (n / (n < 128 ? n : 128)) * (n / (n < 128 ? n : 128)) > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "haar_inverse: too many squares");
+  return launch_haar_inverse(coef, pix, n, squares, static_cast<hipStream_t>(stream));
 }
 
 int rrt_topk_workspace(int64_t rows, int64_t len, int k, size_t* bytes) {
@@ -194,11 +194,11 @@ int rrt_haar_phase_shift(const float* coef_in, int n, const float* rot, int nrot
   const size_t cells = size_t(6) * n * n;
   float* pix = static_cast<float*>(ws);
   float* rotated = reinterpret_cast<float*>(static_cast<char*>(ws) + align256(cells * sizeof(float)));
-  int st = launch_haar_inverse(coef_in, pix, n, 1, s);
+  int st = launch_haar_inverse(coef_in, pix, n, 6, s);
   if (st) return st;
   st = launch_rotate_pixels(pix, rot, nrot, n, rotated, s);
   if (st) return st;
-  return launch_haar_forward(rotated, coef_out, n, nrot, s);
+  return launch_haar_forward(rotated, coef_out, n, int64_t(6) * nrot, s);
 }
 
 int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
@@ -236,10 +236,10 @@ int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_
   char* base = static_cast<char*>(ws);
   float* dense = reinterpret_cast<float*>(base + w.dense_off);
   void* src = base + w.src_off;
-  st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, dense, s);
+  st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, 6, dense, s);
   if (st) return st;
-  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, s)
-           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 1, s);
+  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, 6, s)
+           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 6, s);
   if (st || !(flags & RRT_CHAIN_RULE)) return st;
   // the staging buffer is free now: it takes the 2x2 block coefficients
   return launch_source_blocks(src, f16, L->n, dense, s);
@@ -295,6 +295,109 @@ int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport*
   st = rrt_relight_prepare(L, flags, ws, ws_bytes, stream);
   if (st) return st;
   return rrt_relight_prepared(L, R, T, radiance, flags, ws, ws_bytes, stream);
+}
+
+// Workspace of the lat-long relight: [dense staging 2H^2 float][source map
+// 2H^2 float|half][rule tables 7H float]
+struct LatLongWs {
+  size_t dense_off, src_off, grid_off, total;
+};
+
+static LatLongWs latlong_ws(int H, bool f16) {
+  const size_t cells = size_t(2) * H * H;
+  LatLongWs w;
+  w.dense_off = 0;
+  w.src_off = align256(cells * sizeof(float));
+  w.grid_off = w.src_off + align256(cells * (f16 ? sizeof(__half) : sizeof(float)));
+  w.total = w.grid_off + align256(size_t(latlong_grid_floats(H)) * sizeof(float));
+  return w;
+}
+
+static int validate_latlong(const rrt_light* L, const rrt_latlong_rotations* R,
+                            const rrt_transport* T) {
+  if (!L || !R || !T) return fail(RRT_ERR_INVALID, "relight_latlong: null descriptor");
+  if (!valid_n(L->n, 4) || L->n > 512)
+    return fail(RRT_ERR_INVALID, "relight_latlong: H=%d not a power of two in [4,512]", L->n);
+  const int64_t cells = int64_t(2) * L->n * L->n;
+  if (L->k < 1 || L->k > cells)
+    return fail(RRT_ERR_INVALID, "relight_latlong: light k=%d not in [1,%lld]", L->k, (long long)cells);
+  if (!L->idx || !L->val) return fail(RRT_ERR_INVALID, "relight_latlong: null lighting pointer");
+  if (L->dtype != RRT_F32 && L->dtype != RRT_F16)
+    return fail(RRT_ERR_UNSUPPORTED, "relight_latlong: lighting dtype %d (F32 or F16 only)", L->dtype);
+  if (T->nvert < 0 || T->nvert > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "relight_latlong: nvert=%lld out of range", (long long)T->nvert);
+  if (T->nnz < 1 || T->nnz > cells)
+    return fail(RRT_ERR_INVALID, "relight_latlong: nnz=%d not in [1,%lld]", T->nnz, (long long)cells);
+  if (T->nvert > 0 && !T->idx && T->nnz != cells)
+    return fail(RRT_ERR_INVALID, "relight_latlong: dense transport needs nnz = 2 H^2 = %lld", (long long)cells);
+  if (T->nvert > 0 && (!T->val || !R->elev || !R->shift))
+    return fail(RRT_ERR_INVALID, "relight_latlong: null transport values or rotations");
+  if (T->dtype != RRT_F32 && T->dtype != RRT_BF16 && T->dtype != RRT_E4M3 && T->dtype != RRT_S16)
+    return fail(RRT_ERR_UNSUPPORTED, "relight_latlong: transport dtype %d", T->dtype);
+  if ((T->dtype == RRT_E4M3 || T->dtype == RRT_S16) && !T->block_scale && T->nvert > 0)
+    return fail(RRT_ERR_INVALID, "relight_latlong: block-scaled transport needs block_scale");
+  if (T->cluster || T->brdf)
+    return fail(RRT_ERR_UNSUPPORTED, "relight_latlong: cluster supports and brdf not supported");
+  return RRT_OK;
+}
+
+int rrt_relight_latlong_workspace(const rrt_light* L, size_t* bytes) {
+  if (!L || !bytes) return fail(RRT_ERR_INVALID, "relight_latlong_workspace: null argument");
+  if (!valid_n(L->n, 4) || L->n > 512)
+    return fail(RRT_ERR_INVALID, "relight_latlong: H=%d not a power of two in [4,512]", L->n);
+  *bytes = latlong_ws(L->n, L->dtype == RRT_F16).total;
+  return RRT_OK;
+}
+
+int rrt_relight_latlong(const rrt_light* L, const rrt_latlong_rotations* R, const rrt_transport* T,
+                        float* radiance, unsigned flags, void* ws, size_t ws_bytes, void* stream) {
+  int st = validate_latlong(L, R, T);
+  if (st) return st;
+  if (flags & ~RRT_COMPENSATED)
+    return fail(RRT_ERR_INVALID, "relight_latlong: flags 0x%x (only RRT_COMPENSATED)", flags);
+  const bool f16 = L->dtype == RRT_F16;
+  const LatLongWs w = latlong_ws(L->n, f16);
+  st = check_ws(ws, ws_bytes, w.total, "relight_latlong");
+  if (st) return st;
+  if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight_latlong: null radiance");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* dense = reinterpret_cast<float*>(base + w.dense_off);
+  void* src = base + w.src_off;
+  float* grid = reinterpret_cast<float*>(base + w.grid_off);
+  st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, 2, dense, s);
+  if (st) return st;
+  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, 2, s)
+           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 2, s);
+  if (st) return st;
+  st = launch_latlong_grid(L->n, grid, s);
+  if (st || T->nvert == 0) return st;
+  RelightLaunch a;
+  a.src = src;
+  a.src_f16 = f16;
+  a.vert_rot = nullptr;
+  a.frame_rot = nullptr;
+  a.t_idx = T->idx;
+  a.t_val = T->val;
+  a.t_scale = T->block_scale;
+  a.cluster = nullptr;
+  a.nclusters = 0;
+  a.t_dtype = T->dtype;
+  a.nnz = T->nnz;
+  a.nvert = T->nvert;
+  a.nframes = 1;
+  a.n = L->n;
+  a.flags = flags;
+  a.out = radiance;
+  a.blocks = nullptr;
+  a.brdf = nullptr;
+  a.material = nullptr;
+  a.nmaterials = 0;
+  a.latlong = true;
+  a.ll_elev = R->elev;
+  a.ll_shift = R->shift;
+  a.ll_grid = grid;
+  return launch_relight(a, s);
 }
 
 int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst, float* block_scale,

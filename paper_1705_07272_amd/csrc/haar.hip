@@ -181,31 +181,31 @@ __global__ __launch_bounds__(kThreads) void haar_inv_tiles(const float* coef, co
 
 }  // namespace
 
-int launch_haar_forward(const float* pix, float* coef, int n, int64_t count, hipStream_t s) {
-  if (count == 0) return RRT_OK;
+int launch_haar_forward(const float* pix, float* coef, int n, int64_t squares, hipStream_t s) {
+  if (squares == 0) return RRT_OK;
   const int Q = n < kTile ? n : kTile;
   const int G = n / Q;
-  const int64_t grid = count * 6 * G * G;
+  const int64_t grid = squares * G * G;
   hipLaunchKernelGGL(haar_fwd_tiles, dim3(unsigned(grid)), dim3(kThreads),
                      size_t(Q) * Q * sizeof(float), s, pix, coef, n, ilog2(Q), G);
   int st = check_launch("haar_fwd_tiles");
   if (st || G == 1) return st;
-  hipLaunchKernelGGL(haar_fwd_coarse, dim3(unsigned(count * 6)), dim3(64), 0, s, coef, n, G);
+  hipLaunchKernelGGL(haar_fwd_coarse, dim3(unsigned(squares)), dim3(64), 0, s, coef, n, G);
   return check_launch("haar_fwd_coarse");
 }
 
-int launch_haar_inverse(const float* coef, float* pix, int n, int64_t count, hipStream_t s) {
-  if (count == 0) return RRT_OK;
+int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s) {
+  if (squares == 0) return RRT_OK;
   const int Q = n < kTile ? n : kTile;
   const int G = n / Q;
   const int64_t rs = int64_t(Q) * n, cs = Q;       // first texel of each output tile
   if (G > 1) {
-    hipLaunchKernelGGL(haar_inv_coarse, dim3(unsigned(count * 6)), dim3(64), 0, s, coef, pix, n,
+    hipLaunchKernelGGL(haar_inv_coarse, dim3(unsigned(squares)), dim3(64), 0, s, coef, pix, n,
                        G, rs, cs);
     int st = check_launch("haar_inv_coarse");
     if (st) return st;
   }
-  const int64_t grid = count * 6 * G * G;
+  const int64_t grid = squares * G * G;
   hipLaunchKernelGGL(haar_inv_tiles<float>, dim3(unsigned(grid)), dim3(kThreads),
                      size_t(Q) * Q * sizeof(float), s, coef, (const float*)pix, pix, n, ilog2(Q),
                      G, rs, cs);
@@ -214,17 +214,18 @@ int launch_haar_inverse(const float* coef, float* pix, int n, int64_t count, hip
 
 // `coef` is the caller's own dense staging buffer: for n > 128 its Mallat
 // corner is overwritten by the tile sums (spatial order).
-int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n,
+int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
                             hipStream_t s) {
   const int Q = n < kTile ? n : kTile;
   const int G = n / Q;
   const int64_t rs = n, cs = 1;
   if (G > 1) {
-    hipLaunchKernelGGL(haar_inv_coarse, dim3(6), dim3(64), 0, s, coef, staging, n, G, rs, cs);
+    hipLaunchKernelGGL(haar_inv_coarse, dim3(unsigned(squares)), dim3(64), 0, s, coef, staging, n,
+                       G, rs, cs);
     int st = check_launch("haar_inv_coarse");
     if (st) return st;
   }
-  hipLaunchKernelGGL(haar_inv_tiles<__half>, dim3(unsigned(6 * G * G)), dim3(kThreads),
+  hipLaunchKernelGGL(haar_inv_tiles<__half>, dim3(unsigned(squares * G * G)), dim3(kThreads),
                      size_t(Q) * Q * sizeof(float), s, coef, (const float*)staging, pix, n,
                      ilog2(Q), G, rs, cs);
   return check_launch("haar_inv_tiles_f16");

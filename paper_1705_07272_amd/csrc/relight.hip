@@ -93,11 +93,12 @@ struct Slot {
   int logb;   // log2 of the block side of the basis function
 };
 
-__device__ __forceinline__ Slot decode_slot(int idx, int logn) {
+// nf: faces (squares) of the map, 6 for a cube map, 2 for a lat-long map.
+__device__ __forceinline__ Slot decode_slot(int idx, int logn, int nf) {
   Slot s;
   const int n = 1 << logn;
   const int per_face = n << logn;
-  if (idx < 0 || idx >= 6 * per_face) {
+  if (idx < 0 || idx >= nf * per_face) {
     s.face = -1;
     s.pr = s.pc = s.logb = 0;
     return s;
@@ -180,7 +181,49 @@ struct RelightParams {
   const float* brdf;        // triple product: [nmat][6 n^2] texel factor, or NULL
   const int32_t* material;  // [V] row of brdf, or NULL (row 0)
   int nmat;
+  const float* ll_elev;     // lat-long: [V][2] (cos b, sin b)
+  const int32_t* ll_shift;  // lat-long: [V][2] (s_a, s_c)
+  const float* ll_grid;     // lat-long: the rule's binary32 tables (7 H floats)
+  int ll_tab_off;           // lat-long: byte offset of the tables in LDS
 };
+
+// Source texel of destination texel (row i, column jc + ...) of a
+// longitude-latitude map with H = 2^logh rows and W = 2H columns, for the
+// elevation rotation R_x(b) = (cb, sb) followed by the azimuth shift sa
+// (Sec. V.A: p = (sin t sin f, cos t, sin t cos f), g(p) = f(R p)).  jc is the
+// destination column already shifted by s_c.  Every operation is one
+// binary32 operation in this order (no contraction), so the decision is
+// reproducible: q = R_x p, rho = |q_xz|, row = #{k < H : q_y <= C_k},
+// c = #{k < H : q_z <= C_k rho} (C_k = cos(k pi / H), decreasing, so both
+// counts are binary searches), column = c for q_x >= 0, else W - 1 - c.
+// Returns the flat index over the two H x H squares.
+struct LLTab {
+  const float* rs;   // [H] sin of row centres
+  const float* rc;   // [H] cos of row centres
+  const float* cs;   // [2H] sin of column centres
+  const float* cc;   // [2H] cos of column centres
+  const float* bnd;  // [H] cos(k pi / H)
+};
+
+__device__ __forceinline__ unsigned latlong_source(const LLTab& t, int i, int jc, float cb,
+                                                   float sb, int logh, int sa) {
+#pragma clang fp contract(off)
+  const int H = 1 << logh;
+  const float px = t.rs[i] * t.cs[jc];
+  const float py = t.rc[i];
+  const float pz = t.rs[i] * t.cc[jc];
+  const float qy = cb * py - sb * pz;
+  const float qz = sb * py + cb * pz;
+  const float rho = __fsqrt_rn(px * px + qz * qz);
+  int row = 0, c = 0;
+  for (int step = H >> 1; step >= 1; step >>= 1) {
+    row += (qy <= t.bnd[row + step]) ? step : 0;
+    c += (qz <= t.bnd[c + step] * rho) ? step : 0;
+  }
+  int col = px >= 0.0f ? c : 2 * H - 1 - c;
+  col = (col + sa) & (2 * H - 1);
+  return (unsigned(col >> logh) << (2 * logh)) + (unsigned(row) << logh) + unsigned(col & (H - 1));
+}
 
 // Unscaled 2x2 levels with block side 2..T inside a thread's T x T tile, in
 // place (S stays at the block corner, H/V/D at the corner + B/2 offsets):
@@ -300,12 +343,12 @@ __device__ __forceinline__ float4 chain_block(float4 c, int sf, float3 d, float3
 // The others (blocks wider than Q, and the face's scaling coefficient) are
 // "coarse": returns 1, key = index of the group's in-place block-sum grid.
 // Returns -1 for entries outside the group or invalid indices.
-template <int Q>
+template <int Q, int NF>
 __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces, int g0, int FG,
                                         int& key) {
   constexpr int LOGQ = __builtin_ctz(Q);
   constexpr int STRIDE = image_stride(Q);
-  const Slot s = decode_slot(idx, logn);
+  const Slot s = decode_slot(idx, logn, NF);
   if (s.face < 0 || !((faces >> s.face) & 1u)) return -1;
   const int rank = __popc(faces & ((1u << s.face) - 1u)) - g0;
   if (rank < 0 || rank >= FG) return -1;
@@ -323,8 +366,11 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
 // CHAIN: the finest level comes from the chain rule on the source blocks
 // (Q = 32 only) instead of the exact resampling.  BRDF: triple product, the
 // rotated texels are multiplied by the vertex's BRDF factor (not with CHAIN).
-template <int Q, typename SrcT, bool CHAIN, bool BRDF>
+// LL: the map is a longitude-latitude map (two squares, one frame, the
+// elevation-plus-shift rotation of latlong_source) instead of a cube map.
+template <int Q, typename SrcT, bool CHAIN, bool BRDF, bool LL>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
+  constexpr int NF = LL ? 2 : 6;  // faces (squares) of the map
   constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
   constexpr int T = Q / TS;           // texels per tile side
   constexpr int LOGQ = __builtin_ctz(Q);
@@ -341,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   const int G2 = G * G;
   const int FG = p.group_faces;
   const __amdgpu_buffer_rsrc_t src =
-      source_resource(static_cast<const SrcT*>(p.src), 6 * (n << logn));
+      source_resource(static_cast<const SrcT*>(p.src), NF * (n << logn));
   const float eps = quotient_margin(logn);
   const bool comp = p.comp != 0;
 
@@ -378,11 +424,11 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   unsigned m = 0;
   for (int e = lane; e < nnz; e += kThreads) {
     const int idx = idx_row ? idx_row[e] : e;
-    if (idx >= 0 && idx < 6 * (n << logn)) m |= 1u << (idx >> (2 * logn));
+    if (idx >= 0 && idx < NF * (n << logn)) m |= 1u << (idx >> (2 * logn));
   }
   unsigned faces = 0;
 #pragma unroll
-  for (int f = 0; f < 6; ++f) faces |= (__ballot((m >> f) & 1u) ? 1u : 0u) << f;
+  for (int f = 0; f < NF; ++f) faces |= (__ballot((m >> f) & 1u) ? 1u : 0u) << f;
   const int nf = __popc(faces);
   const int ngroups = (nf + FG - 1) / FG;
 
@@ -392,10 +438,28 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   const uint64_t lanes_below = (uint64_t(1) << lane) - 1;
   int nfine = 0, ncoarse = 0;
 
+  // lat-long: the rule's tables into LDS, this vertex's rotation
+  LLTab tab = {};
+  float llcb = 0.0f, llsb = 0.0f;
+  int llsa = 0, llsc = 0;
+  if constexpr (LL) {
+    float* t = reinterpret_cast<float*>(dyn_lds + p.ll_tab_off);
+    for (int k = lane; k < 7 * n; k += kThreads) t[k] = p.ll_grid[k];
+    tab = {t, t + n, t + 2 * n, t + 4 * n, t + 6 * n};
+    llcb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(p.ll_elev[2 * v])));
+    llsb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(p.ll_elev[2 * v + 1])));
+    llsa = __builtin_amdgcn_readfirstlane(p.ll_shift[2 * v]) & (2 * n - 1);
+    llsc = __builtin_amdgcn_readfirstlane(p.ll_shift[2 * v + 1]) & (2 * n - 1);
+    wave_sync();
+  }
+
   for (int f = 0; f < p.nframes; ++f) {
-    IRot R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr);
+    IRot R = {};
+    if constexpr (!LL) {
+      R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) R.m[k] = __builtin_amdgcn_readfirstlane(R.m[k]);
+      for (int k = 0; k < 9; ++k) R.m[k] = __builtin_amdgcn_readfirstlane(R.m[k]);
+    }
     Acc acc = {0.0f, 0.0f};
 
     for (int grp = 0; grp < ngroups; ++grp) {
@@ -410,7 +474,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         for (int c0 = 0; c0 < listed; c0 += kThreads) {
           const int e = c0 + lane;
           int key = 0, kind = -1;
-          if (e < listed) kind = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+          if (e < listed) kind = classify<Q, NF>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
           const uint64_t bf = __ballot(kind == 0), bc = __ballot(kind == 1);
           if (kind >= 0) {
             const int at = kind == 0 ? nfine + __popcll(bf & lanes_below)
@@ -441,7 +505,26 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         const int hz = wrap_mad(ax.mU.z, Uh, wrap_mad(ax.mV.z, Vh, wrap_mad(ax.mN.z, hn, 0)));
         for (int by = 0; by < G; ++by) {
           for (int bx = 0; bx < G; ++bx, ++gi) {
-            if constexpr (CHAIN) {
+            if constexpr (LL) {
+              // the same compact patches, through the lat-long rule
+              if (owns_tile) {
+                float val[T][T];
+#pragma unroll
+                for (int a = 0; a < T; ++a)
+#pragma unroll
+                  for (int b = 0; b < T; ++b) {
+                    const int i = by * Q + TS * a + ty;
+                    const int jc = (face * n + bx * Q + TS * b + tx + llsc) & (2 * n - 1);
+                    val[a][b] = load_src<SrcT>(
+                        src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa)
+                                 << (sizeof(SrcT) == 4 ? 2 : 1));
+                  }
+#pragma unroll
+                for (int a = 0; a < T; ++a)
+#pragma unroll
+                  for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
+              }
+            } else if constexpr (CHAIN) {
               // Destination 2x2 blocks (8 a + ty, 8 b + tx) of the 16 x 16 in
               // this block: the source block by the exact map at n / 2, then
               // the chain rule; level-1 coefficients go straight to the image.
@@ -590,7 +673,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             // entries past the list
             for (int e = listed + lane; e < nnz; e += kThreads) {
               int key = 0;
-              const int kind = classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
+              const int kind = classify<Q, NF>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
               if (kind == 0 && ((key >> kOffBits) & ((1 << kBlockBits) - 1)) == gi)
                 acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e),
                         ldexpf(img[key & ((1 << kOffBits) - 1)], -(key >> kLogbShift)), comp);
@@ -626,7 +709,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
       }
       for (int e = listed + lane; e < nnz; e += kThreads) {
         int key = 0;
-        if (classify<Q>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key) == 1)
+        if (classify<Q, NF>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key) == 1)
           acc_add(acc, transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e), float(gS[key]),
                   comp);
       }
@@ -680,6 +763,24 @@ __global__ void source_blocks_kernel(const SrcT* __restrict__ src, int logn,
                           0.5f * ((a + b) - (c + d)), 0.5f * ((a - b) - (c - d)));
 }
 
+// The lat-long rule's tables: binary32 roundings of sin / cos of the row and
+// column centres ((k + 1/2) pi / H) and of the boundary cosines cos(k pi / H),
+// evaluated in double precision.
+__global__ void latlong_grid_kernel(int H, float* __restrict__ grid) {
+  constexpr double kPi = 3.141592653589793;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const double centre = (k + 0.5) * kPi / H;
+  if (k < H) {
+    grid[k] = float(sin(centre));
+    grid[H + k] = float(cos(centre));
+    grid[6 * H + k] = float(cos(k * kPi / H));
+  }
+  if (k < 2 * H) {
+    grid[2 * H + k] = float(sin(centre));
+    grid[4 * H + k] = float(cos(centre));
+  }
+}
+
 // Index of coefficient idx at resolution n in the map n >> levels, or -1 for
 // the `levels` finest levels (Mallat layout: the coarse levels are the
 // top-left corner of each face).
@@ -722,12 +823,17 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   dst[int64_t(r) * 6 * per_face + q] = src[min(at, unsigned(6 * per_face - 1))];
 }
 
-template <int Q, typename SrcT, bool CHAIN = false, bool BRDF = false>
-int launch_q(const RelightParams& prm, int64_t nvert, hipStream_t s) {
+template <int Q, typename SrcT, bool CHAIN = false, bool BRDF = false, bool LL = false>
+int launch_q(const RelightParams& prm_in, int64_t nvert, hipStream_t s) {
+  RelightParams prm = prm_in;
   const int G = (1 << prm.logn) / Q;
-  const size_t lds = ((size_t(Q) * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) & ~size_t(7)) +
-                     size_t(prm.group_faces) * G * G * 8;
-  hipLaunchKernelGGL((relight_kernel<Q, SrcT, CHAIN, BRDF>), dim3(unsigned(nvert)),
+  size_t lds = ((size_t(Q) * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) & ~size_t(7)) +
+               size_t(prm.group_faces) * G * G * 8;
+  if (LL) {
+    prm.ll_tab_off = int(lds);
+    lds += size_t(latlong_grid_floats(1 << prm.logn)) * 4;
+  }
+  hipLaunchKernelGGL((relight_kernel<Q, SrcT, CHAIN, BRDF, LL>), dim3(unsigned(nvert)),
                      dim3(kThreads), lds, s, prm);
   return check_launch("relight_kernel");
 }
@@ -744,7 +850,19 @@ int launch_size(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
 }
 
 template <typename SrcT>
-int launch_src(const RelightParams& prm, int n, int64_t nvert, bool chain, hipStream_t s) {
+int launch_latlong(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
+  switch (n < kBlock ? n : kBlock) {
+    case 4: return launch_q<4, SrcT, false, false, true>(prm, nvert, s);
+    case 8: return launch_q<8, SrcT, false, false, true>(prm, nvert, s);
+    case 16: return launch_q<16, SrcT, false, false, true>(prm, nvert, s);
+    default: return launch_q<kBlock, SrcT, false, false, true>(prm, nvert, s);
+  }
+}
+
+template <typename SrcT>
+int launch_src(const RelightParams& prm, int n, int64_t nvert, bool chain, bool latlong,
+               hipStream_t s) {
+  if (latlong) return launch_latlong<SrcT>(prm, n, nvert, s);
   if (chain) return launch_q<kBlock, SrcT, true>(prm, nvert, s);
   return prm.brdf ? launch_size<SrcT, true>(prm, n, nvert, s)
                   : launch_size<SrcT, false>(prm, n, nvert, s);
@@ -773,19 +891,24 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   p.listed = a.nnz < kMaxListed ? a.nnz : kMaxListed;
   const int G = a.n < kBlock ? 1 : a.n / kBlock;
   const int fit = kGroupBytes / (G * G * 8);
-  p.group_faces = fit < 1 ? 1 : (fit > 6 ? 6 : fit);
+  const int nf = a.latlong ? 2 : 6;
+  p.group_faces = fit < 1 ? 1 : (fit > nf ? nf : fit);
   p.blocks = static_cast<const float4*>(a.blocks);
   p.brdf = a.brdf;
   p.material = a.material;
   p.nmat = a.nmaterials;
+  p.ll_elev = a.ll_elev;
+  p.ll_shift = a.ll_shift;
+  p.ll_grid = a.ll_grid;
+  p.ll_tab_off = 0;
   const bool chain = (a.flags & RRT_CHAIN_RULE) != 0;
-  return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, chain, s)
-                   : launch_src<float>(p, a.n, a.nvert, chain, s);
+  return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, chain, a.latlong, s)
+                   : launch_src<float>(p, a.n, a.nvert, chain, a.latlong, s);
 }
 
-int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n,
+int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n, int squares,
                          float* dense, hipStream_t s) {
-  const int64_t total = int64_t(6) * n * n;
+  const int64_t total = int64_t(squares) * n * n;
   hipLaunchKernelGGL(fill_zero, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, dense, total);
   int st = check_launch("fill_zero");
   if (st) return st;
@@ -806,6 +929,12 @@ int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStr
                        reinterpret_cast<float4*>(blocks));
   }
   return check_launch("source_blocks");
+}
+
+int launch_latlong_grid(int H, float* grid, hipStream_t s) {
+  hipLaunchKernelGGL(latlong_grid_kernel, dim3(unsigned((2 * H + 255) / 256)), dim3(256), 0, s, H,
+                     grid);
+  return check_launch("latlong_grid");
 }
 
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,

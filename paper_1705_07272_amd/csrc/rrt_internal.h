@@ -24,10 +24,11 @@ inline int ilog2(int64_t x) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Haar transform launchers (haar.hip).
-int launch_haar_forward(const float* pix, float* coef, int n, int64_t count, hipStream_t s);
-int launch_haar_inverse(const float* coef, float* pix, int n, int64_t count, hipStream_t s);
+// squares: number of n x n squares (a cube map is 6, a longitude-latitude map 2)
+int launch_haar_forward(const float* pix, float* coef, int n, int64_t squares, hipStream_t s);
+int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s);
 // Inverse transform writing binary16 pixels (source map of the F16 form).
-int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n,
+int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
                             hipStream_t s);
 
 // Selection (topk.hip).
@@ -36,14 +37,15 @@ int launch_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, 
                 void* ws, hipStream_t s);
 
 // Coefficient scatter into a zeroed dense map (relight.hip).
-int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n,
+// squares: 6 (cube map) or 2 (longitude-latitude map)
+int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n, int squares,
                          float* dense, hipStream_t s);
 // Pixel-domain rotation of one map for a batch of rotations (relight.hip).
 int launch_rotate_pixels(const float* src, const float* rot, int nrot, int n, float* dst,
                          hipStream_t s);
 
 struct RelightLaunch {
-  const void* src;          // [6][n][n] float32 or binary16 source map
+  const void* src;          // [6][n][n] (or [2][n][n] lat-long) float32 or binary16 source map
   bool src_f16;
   const float* vert_rot;    // [V][9]
   const float* frame_rot;   // [F][9] or nullptr
@@ -63,7 +65,16 @@ struct RelightLaunch {
   const float* brdf;        // triple product: [M][6 n^2] texel factor, or NULL
   const int32_t* material;  // [V] row of brdf, or NULL (row 0)
   int nmaterials;
+  // longitude-latitude map (then vert_rot, frame_rot, cluster, brdf unused, nframes = 1)
+  bool latlong = false;
+  const float* ll_elev = nullptr;    // [V][2] (cos b, sin b)
+  const int32_t* ll_shift = nullptr; // [V][2] (s_a, s_c)
+  const float* ll_grid = nullptr;    // latlong_grid_floats(n) binary32 tables
 };
+// Tables of the longitude-latitude rule: row sines, row cosines [H], column
+// sines, column cosines [2H], boundary cosines [H]; 7 H floats.
+inline int latlong_grid_floats(int H) { return 7 * H; }
+int launch_latlong_grid(int H, float* grid, hipStream_t s);
 int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStream_t s);
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
                            hipStream_t s);

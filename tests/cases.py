@@ -83,3 +83,25 @@ def triple_case(w, materials, vertex_ids=None, batch=64):
                 frame_rot=frame_rotations(w), brdf=brdf_pixels(w, materials).astype(np.float32),
                 material=material_ids(w, materials)[vertex_ids],
                 t_idx=np.concatenate(idx_parts), t_val=np.concatenate(val_parts))
+
+
+def latlong_case(w, vertex_ids=None):
+    """Stored inputs of a longitude-latitude workload (scenes.latlong): the
+    checker's top-k lighting and top-nnz transport rows over [2, H, H], and
+    the vertices' (cos b, sin b) and azimuth shifts."""
+    from scenes.latlong import lighting_pixels as ll_pixels
+    from scenes.latlong import phong_exponents as ll_exps
+    from scenes.latlong import rotations as ll_rotations
+    from scenes.latlong import transport_pixels as ll_transport
+    vertex_ids = np.arange(w.nverts) if vertex_ids is None else np.asarray(vertex_ids)
+    li, lv = lighting_coefficients(ll_pixels(w.cfg, w.H), w.k_light)
+    elev, shift = ll_rotations(w)
+    exps = ll_exps(w)
+    idx_parts, val_parts = [], []
+    for s in range(0, len(vertex_ids), 64):
+        vids = vertex_ids[s:s + 64]
+        i, v = transport_rows(ll_transport(w, exps[vids], vids), w.nnz)
+        idx_parts.append(i)
+        val_parts.append(v)
+    return dict(H=w.H, light_idx=li, light_val=lv, elev=elev[vertex_ids], shift=shift[vertex_ids],
+                t_idx=np.concatenate(idx_parts), t_val=np.concatenate(val_parts))

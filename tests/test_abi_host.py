@@ -232,3 +232,35 @@ def test_triple_product_validation(rrt):
     assert lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8),
                                     E.RRT_CHAIN_RULE, _p(256), 1 << 30,
                                     None) == E.RRT_ERR_UNSUPPORTED
+
+
+def test_latlong_validation(rrt):
+    """Lat-long relight: H a power of two in [4, 512], sizes over 2 H^2,
+    no cluster or brdf, flags RRT_COMPENSATED only, workspace checked."""
+    E = rrt._abi
+    lib = rrt.lib
+
+    def call(H=16, k=10, nnz=16, nvert=5, cluster=0, brdf=0, flags=0, ws=256, wsb=1 << 20,
+             elev=8, shift=8):
+        L = E.Light(H, k, 8, 8, 0)
+        R = E.LatLongRotations(elev, shift)
+        T = E.Transport(nvert, nnz, 8, 8, 0, 0, cluster, 1 if cluster else 0, brdf, 0,
+                        1 if brdf else 0)
+        return lib.rrt_relight_latlong(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8),
+                                       flags, _p(ws), wsb, None)
+
+    nb = ctypes.c_size_t(0)
+    L = E.Light(16, 10, 8, 8, 0)
+    assert lib.rrt_relight_latlong_workspace(ctypes.byref(L), ctypes.byref(nb)) == E.RRT_OK
+    cells = 2 * 16 * 16
+    assert nb.value == 2 * ((cells * 4 + 255) // 256 * 256) + 512
+    assert call(H=2) == E.RRT_ERR_INVALID
+    assert call(H=12) == E.RRT_ERR_INVALID
+    assert call(H=1024) == E.RRT_ERR_INVALID
+    assert call(k=cells + 1) == E.RRT_ERR_INVALID
+    assert call(nnz=cells + 1) == E.RRT_ERR_INVALID
+    assert call(cluster=8) == E.RRT_ERR_UNSUPPORTED
+    assert call(brdf=256) == E.RRT_ERR_UNSUPPORTED
+    assert call(flags=E.RRT_CHAIN_RULE) == E.RRT_ERR_INVALID
+    assert call(wsb=64) == E.RRT_ERR_WORKSPACE
+    assert call(elev=0) == E.RRT_ERR_INVALID

@@ -183,3 +183,34 @@ def test_full_cube128_v50000_triple_product(rrt):
     err = max(frame_errors(out.cpu().numpy()[:, sample], ref))
     print(f"cube128 V=50000 triple product, 8 materials: sampled rel-L2 {err:.3e}")
     assert err <= 1e-5
+
+
+def test_full_latlong128_v50000(rrt):
+    """Lat-long 128 x 256, top-1024 lighting, 50,000 vertices, CSR-256: the
+    launch the bench times, sampled outputs against the checker."""
+    from cases import frame_errors, latlong_case
+    from oracle.latlong import relight_latlong
+    from scenes.latlong import LATLONG_WORKLOADS, phong_exponents, rotations, transport_pixels_torch
+    w = LATLONG_WORKLOADS[6]
+    sample = _sample(w.nverts, 40, 6)
+    case = latlong_case(w, sample)
+    exps = phong_exponents(w)
+    idx = torch.empty((w.nverts, w.nnz), dtype=torch.int32, device="cuda")
+    val = torch.empty((w.nverts, w.nnz), dtype=torch.float32, device="cuda")
+    for s in range(0, w.nverts, 2048):
+        e = min(w.nverts, s + 2048)
+        T = transport_pixels_torch(w, exps[s:e], np.arange(s, e), "cuda", dtype=torch.float32)
+        idx[s:e], val[s:e] = rrt.project_rows(T.contiguous(), w.nnz)
+    sel = torch.from_numpy(sample).cuda().long()
+    idx[sel] = torch.from_numpy(case["t_idx"]).cuda()
+    val[sel] = torch.from_numpy(case["t_val"]).cuda()
+    elev, shift = rotations(w)
+    out = rrt.relight_latlong(w.H, torch.from_numpy(case["light_idx"]).cuda(),
+                              torch.from_numpy(case["light_val"]).cuda(),
+                              torch.from_numpy(elev).cuda(), torch.from_numpy(shift).cuda(), idx, val)
+    torch.cuda.synchronize()
+    ref = relight_latlong(case["light_idx"], case["light_val"], w.H, case["elev"], case["shift"],
+                          case["t_idx"], case["t_val"])
+    err = max(frame_errors(out.cpu().numpy()[None, sample], ref))
+    print(f"latlong 128x256 V=50000 sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5

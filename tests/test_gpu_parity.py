@@ -479,3 +479,108 @@ def test_relight_triple_edge_cases(rrt):
         rrt.relight(n, dev(case["light_idx"]), dev(case["light_val"]), dev(case["vert_rot"]),
                     dev(case["t_idx"]), dev(case["t_val"]), brdf=dev(case["brdf"]),
                     material=dev(case["material"]), chain_rule=True)
+
+
+# ---------------------------------------------------------------- lat-long map (f4)
+def _ll_workload(cfg, H, k, V, nnz):
+    from scenes.latlong import LatLongWorkload
+    return LatLongWorkload(cfg, f"test{cfg}", H, k, V, nnz, 1.0, 200.0)
+
+
+def run_latlong(rrt, case, **kw):
+    out = rrt.relight_latlong(case["H"], dev(case["light_idx"]), dev(case["light_val"]),
+                              dev(case["elev"]), dev(case["shift"]), dev(case["t_idx"]),
+                              dev(case["t_val"]), **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[None, :]
+
+
+@pytest.mark.parametrize("H", [4, 16, 128, 512])
+def test_latlong_grid_tables_exact(rrt, H):
+    """The device's binary32 tables equal the checker's bit for bit."""
+    from oracle.latlong import grid
+    case = dict(H=H, light_idx=np.array([0], np.int32), light_val=np.array([1.0], np.float32),
+                elev=np.array([[1.0, 0.0]], np.float32), shift=np.zeros((1, 2), np.int32),
+                t_idx=np.array([[0]], np.int32), t_val=np.array([[1.0]], np.float32))
+    cells = 2 * H * H
+    off = 2 * (((cells * 4) + 255) // 256 * 256)
+    ws = torch.zeros(off + (7 * H * 4 + 255) // 256 * 256, dtype=torch.uint8, device="cuda")
+    rrt.relight_latlong(H, dev(case["light_idx"]), dev(case["light_val"]), dev(case["elev"]),
+                        dev(case["shift"]), dev(case["t_idx"]), dev(case["t_val"]), workspace=ws)
+    torch.cuda.synchronize()
+    got = ws[off:off + 7 * H * 4].cpu().view(torch.float32).numpy()
+    want = np.concatenate(grid(H))
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("H,V,nnz,k,comp", [(4, 9, 20, 32, False), (8, 17, 64, 128, False),
+                                            (16, 23, 128, 256, True), (32, 31, 256, 1024, False),
+                                            (64, 29, 256, 1024, False), (128, 19, 256, 1024, True),
+                                            (256, 7, 256, 2048, False)])
+def test_relight_latlong(rrt, H, V, nnz, k, comp):
+    """Lat-long relighting against the checker's binary32 rule + FP64 levels
+    and dot on the same stored inputs."""
+    from cases import latlong_case
+    from oracle.latlong import relight_latlong
+    case = latlong_case(_ll_workload(900 + H, H, k, V, nnz))
+    ref = relight_latlong(case["light_idx"], case["light_val"], H, case["elev"], case["shift"],
+                          case["t_idx"], case["t_val"], return_scale=True)
+    check_frames(run_latlong(rrt, case, compensated=comp), ref, rel_l2=H >= 32)
+
+
+@pytest.mark.parametrize("H", [16, 64, 128])
+def test_relight_latlong_gather_exact(rrt, H):
+    """Source-index exactness of the lat-long rule: a texel-ID lighting and
+    rows holding one finest-level H, V or D coefficient each, so a radiance
+    is (+-a +-b +-c +-d)/2 of four gathered source indices; random and
+    boundary-heavy elevations (b = 0, pi/2, pi, pi/4) with shifts."""
+    from oracle.haar import haar_forward
+    from oracle.latlong import rotate
+    ids = np.arange(2 * H * H, dtype=np.float64).reshape(2, H, H)
+    light = haar_forward(ids).ravel().astype(np.float32)
+    light_idx = np.arange(2 * H * H, dtype=np.int32)
+    h = H // 2
+    rr, cc = np.meshgrid(np.arange(h), np.arange(h), indexing="ij")
+    pos = [f * H * H + (rr + dr) * H + (cc + dc) for f in range(2) for dr, dc in [(0, h), (h, 0), (h, h)]]
+    rows = np.concatenate([p_.ravel() for p_ in pos]).astype(np.int32)
+    V = rows.size
+    rng = np.random.default_rng(H)
+    elevs = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (np.cos(np.pi / 4), np.sin(np.pi / 4))]
+    elevs += [(np.cos(b), np.sin(b)) for b in np.arccos(rng.uniform(-1, 1, 3))]
+    for cb, sb in elevs:
+        e = np.array([cb, sb], np.float32)
+        sh = rng.integers(-3 * H, 3 * H, 2).astype(np.int32)
+        out = rrt.relight_latlong(H, dev(light_idx), dev(light), dev(np.tile(e, (V, 1))),
+                                  dev(np.tile(sh, (V, 1))), dev(rows.reshape(V, 1)),
+                                  dev(np.ones((V, 1), np.float32)))
+        got = out.cpu().numpy()
+        want = haar_forward(rotate(ids, e[0], e[1], sh[0], sh[1])).ravel()[rows]
+        err = np.abs(got - want)
+        assert err.max() < 0.05, (e, sh, int((err >= 0.05).sum()), float(err.max()))
+
+
+def test_relight_latlong_edge_cases(rrt):
+    """Empty vertex set; shifts reduced mod 2H; binary16 lighting; out-of-range
+    transport entries ignored."""
+    from cases import latlong_case
+    from oracle.latlong import relight_latlong
+    H = 32
+    case = latlong_case(_ll_workload(950, H, 512, 12, 128))
+    empty = dict(case, elev=case["elev"][:0], shift=case["shift"][:0], t_idx=case["t_idx"][:0],
+                 t_val=case["t_val"][:0])
+    assert run_latlong(rrt, empty).shape == (1, 0)
+    base = run_latlong(rrt, case)
+    wrapped = run_latlong(rrt, dict(case, shift=case["shift"] + np.array([[4 * H, -6 * H]], np.int32)))
+    assert np.array_equal(base, wrapped)
+    bad = dict(case, t_idx=case["t_idx"].copy())
+    bad["t_idx"][:, 5] = 2 * H * H + 3
+    bad["t_idx"][:, 7] = -1
+    ref = relight_latlong(bad["light_idx"], bad["light_val"], H, bad["elev"], bad["shift"],
+                          bad["t_idx"], bad["t_val"], return_scale=True)
+    check_frames(run_latlong(rrt, bad), ref)
+    half = run_latlong(rrt, dict(case, light_val=case["light_val"].astype(np.float16)),
+                       compensated=True)
+    from cases import frame_errors
+    ref16 = relight_latlong(case["light_idx"], case["light_val"].astype(np.float16), H, case["elev"],
+                            case["shift"], case["t_idx"], case["t_val"])
+    assert max(frame_errors(half, ref16)) <= 2e-3
