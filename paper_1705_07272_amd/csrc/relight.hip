@@ -40,6 +40,9 @@ constexpr int kBlock = 32;
 constexpr int kMaxListed = 512;
 // LDS for the FP64 block sums of the faces processed together.
 constexpr int kGroupBytes = 4096;
+// LDS bit mask of the blocks of a face group that hold listed entries (at
+// most 1,024 blocks: kGroupBytes / 8, or one face of 32 x 32 blocks)
+constexpr int kBlockMaskBytes = 128;
 
 // Gathers from the source map go through a raw buffer resource: 32-bit
 // offsets (no 64-bit address arithmetic per texel) and hardware range
@@ -278,6 +281,25 @@ __device__ __forceinline__ int nth_face(unsigned faces, int k) {
   return face;
 }
 
+// Sum of a lane's T x T gathered texels, pairwise.
+template <int T>
+__device__ __forceinline__ float tile_sum(const float (&v)[T][T]) {
+  float r[T];
+#pragma unroll
+  for (int a = 0; a < T; ++a) {
+    if constexpr (T == 4) {
+      r[a] = (v[a][0] + v[a][1]) + (v[a][2] + v[a][3]);
+    } else if constexpr (T == 2) {
+      r[a] = v[a][0] + v[a][1];
+    } else {
+      r[a] = v[a][0];
+    }
+  }
+  if constexpr (T == 4) return (r[0] + r[1]) + (r[2] + r[3]);
+  if constexpr (T == 2) return r[0] + r[1];
+  return r[0];
+}
+
 // Levels with block side From..T of a thread's tile (the smaller ones are
 // already in place), unscaled as in tile_levels.
 template <int T, int From>
@@ -371,6 +393,11 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
 template <int Q, typename SrcT, bool CHAIN, bool BRDF, bool LL>
 __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   constexpr int NF = LL ? 2 : 6;  // faces (squares) of the map
+  // Blocks holding no listed entry of their own only feed the levels above
+  // them through their sum: with SUM_ONLY such a block skips the image, the
+  // levels inside it and the entry scan (not for CHAIN, whose image holds
+  // level-1 coefficients, nor BRDF, whose factor applies in the tile phase).
+  constexpr bool SUM_ONLY = !CHAIN && !BRDF;
   constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
   constexpr int T = Q / TS;           // texels per tile side
   constexpr int LOGQ = __builtin_ctz(Q);
@@ -395,6 +422,9 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   int* lkey = reinterpret_cast<int*>(dyn_lds + IMG * 4);
   float* lval = reinterpret_cast<float*>(lkey + p.listed);
   double* gS = reinterpret_cast<double*>(dyn_lds + ((IMG * 4 + 8 * p.listed + 7) & ~7));
+  // one bit per block of the face group: the block has listed entries
+  unsigned* bmask = reinterpret_cast<unsigned*>(gS + FG * G2);
+  const int bwords = (FG * G2 + 31) >> 5;
 
   // index row of this vertex: its own, or its cluster's support row
   const int32_t* idx_row = nullptr;
@@ -471,6 +501,10 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         // the front, coarse entries from the back.
         nfine = 0;
         ncoarse = 0;
+        if (SUM_ONLY) {
+          for (int k = lane; k < bwords; k += kThreads) bmask[k] = 0u;
+          wave_sync();
+        }
         for (int c0 = 0; c0 < listed; c0 += kThreads) {
           const int e = c0 + lane;
           int key = 0, kind = -1;
@@ -481,6 +515,10 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
                                      : listed - 1 - (ncoarse + __popcll(bc & lanes_below));
             lkey[at] = key;
             lval[at] = transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e);
+            if (SUM_ONLY && kind == 0) {
+              const int gb = (key >> kOffBits) & ((1 << kBlockBits) - 1);
+              atomicOr(&bmask[gb >> 5], 1u << (gb & 31));
+            }
           }
           nfine += __popcll(bf);
           ncoarse += __popcll(bc);
@@ -505,6 +543,12 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         const int hz = wrap_mad(ax.mU.z, Uh, wrap_mad(ax.mV.z, Vh, wrap_mad(ax.mN.z, hn, 0)));
         for (int by = 0; by < G; ++by) {
           for (int bx = 0; bx < G; ++bx, ++gi) {
+            // entries past the list may fall in any block: then every block is full
+            bool full = true;
+            if constexpr (SUM_ONLY)
+              full = nnz > listed ||
+                     ((__builtin_amdgcn_readfirstlane(bmask[gi >> 5]) >> (gi & 31)) & 1u) != 0u;
+            float lane_sum = 0.0f;  // sum-only blocks: this lane's gathered texels
             if constexpr (LL) {
               // the same compact patches, through the lat-long rule
               if (owns_tile) {
@@ -519,10 +563,14 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
                         src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa)
                                  << (sizeof(SrcT) == 4 ? 2 : 1));
                   }
+                if (full) {
 #pragma unroll
-                for (int a = 0; a < T; ++a)
+                  for (int a = 0; a < T; ++a)
 #pragma unroll
-                  for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
+                    for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
+                } else {
+                  lane_sum = tile_sum<T>(val);
+                }
               }
             } else if constexpr (CHAIN) {
               // Destination 2x2 blocks (8 a + ty, 8 b + tx) of the 16 x 16 in
@@ -595,10 +643,22 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
                 ry = wrap_mad(ax.mV.y, 2 * TS, ry);
                 rz = wrap_mad(ax.mV.z, 2 * TS, rz);
               }
+              if (full) {
 #pragma unroll
-              for (int a = 0; a < T; ++a)
+                for (int a = 0; a < T; ++a)
 #pragma unroll
-                for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
+                  for (int b = 0; b < T; ++b) img[(TS * a + ty) * STRIDE + TS * b + tx] = val[a][b];
+              } else {
+                lane_sum = tile_sum<T>(val);
+              }
+            }
+            if (SUM_ONLY && !full) {
+              // the block's sum for the levels above it; nothing else reads it
+#pragma unroll
+              for (int o = 1; o < kThreads; o <<= 1) lane_sum += __shfl_xor(lane_sum, o, 64);
+              if (lane == 0) gS[gi] = double(lane_sum) * (1.0 / Q);
+              wave_sync();
+              continue;
             }
             wave_sync();
             float s = 0.0f;  // unscaled sum of this lane's tile, then of its block
@@ -828,7 +888,7 @@ int launch_q(const RelightParams& prm_in, int64_t nvert, hipStream_t s) {
   RelightParams prm = prm_in;
   const int G = (1 << prm.logn) / Q;
   size_t lds = ((size_t(Q) * image_stride(Q) * 4 + 8 * size_t(prm.listed) + 7) & ~size_t(7)) +
-               size_t(prm.group_faces) * G * G * 8;
+               size_t(prm.group_faces) * G * G * 8 + kBlockMaskBytes;
   if (LL) {
     prm.ll_tab_off = int(lds);
     lds += size_t(latlong_grid_floats(1 << prm.logn)) * 4;
