@@ -584,3 +584,65 @@ def test_relight_latlong_edge_cases(rrt):
     ref16 = relight_latlong(case["light_idx"], case["light_val"].astype(np.float16), H, case["elev"],
                             case["shift"], case["t_idx"], case["t_val"])
     assert max(frame_errors(half, ref16)) <= 2e-3
+
+
+# ---------------------------------------------------------------- rows x storage forms
+def _decoded(rrt, vals, form):
+    """Device storage conversion of [V, nnz] values and the float32 values the
+    kernel decodes from it (code x scale in binary32), for the checker."""
+    t = dev(vals)
+    if form == "bf16":
+        codes = rrt.convert(t, "bf16")
+        return codes, None, codes.float().cpu().numpy()
+    codes, scale = rrt.convert(t, form)
+    sc = np.repeat(scale.cpu().numpy(), 64, axis=1)[:, :vals.shape[1]]
+    assert form == "s16"
+    return codes, scale, codes.cpu().numpy().astype(np.float32) * sc
+
+
+def test_chain_rule_with_f16_lighting(rrt):
+    """Chain rule with a binary16 lighting (source map and block coefficients
+    from binary16 texels) and compensated accumulation, against the checker
+    fed the same binary16 lighting values: the only extra error is the
+    binary16 rounding of the reconstructed map."""
+    from cases import build_case, frame_errors, workload
+    w = workload(620, 64, 1024, 29, 256)
+    case = build_case(w)
+    case16 = dict(case, light_val=case["light_val"].astype(np.float16))
+    got = rrt.relight(64, dev(case16["light_idx"]), dev(case16["light_val"]), dev(case16["vert_rot"]),
+                      dev(case16["t_idx"]), dev(case16["t_val"]), compensated=True,
+                      chain_rule=True).cpu().numpy()
+    ref, _ = chain_reference(case16)
+    assert max(frame_errors(got, ref)) <= 2e-3
+
+
+def test_triple_product_with_bf16_visibility(rrt):
+    """Triple product with the visibility rows stored in BF16: against the
+    checker on the decoded BF16 values at the FP32 tolerance."""
+    from cases import triple_case, workload
+    from oracle.triple import relight_triple
+    n = 32
+    case = triple_case(workload(780, n, 1024, 19, 256), 3)
+    codes, _, decoded = _decoded(rrt, case["t_val"], "bf16")
+    out = rrt.relight(n, dev(case["light_idx"]), dev(case["light_val"]), dev(case["vert_rot"]),
+                      dev(case["t_idx"]), codes, brdf=dev(case["brdf"]),
+                      material=dev(case["material"])).cpu().numpy()
+    ref = relight_triple(case["light_idx"], case["light_val"], n, case["vert_rot"], None,
+                         case["t_idx"], decoded, case["brdf"], case["material"], return_scale=True)
+    check_frames(out, ref)
+
+
+def test_latlong_with_s16_transport(rrt):
+    """Lat-long relight with S16 block-scaled transport rows: against the
+    checker on the decoded values at the FP32 tolerance."""
+    from cases import latlong_case
+    from oracle.latlong import relight_latlong
+    H = 64
+    case = latlong_case(_ll_workload(960, H, 1024, 21, 256))
+    codes, scale, decoded = _decoded(rrt, case["t_val"], "s16")
+    out = rrt.relight_latlong(H, dev(case["light_idx"]), dev(case["light_val"]), dev(case["elev"]),
+                              dev(case["shift"]), dev(case["t_idx"]), codes, block_scale=scale,
+                              compensated=True).cpu().numpy()[None, :]
+    ref = relight_latlong(case["light_idx"], case["light_val"], H, case["elev"], case["shift"],
+                          case["t_idx"], decoded, return_scale=True)
+    check_frames(out, ref)
