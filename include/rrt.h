@@ -322,6 +322,35 @@ int rrt_adam_step(float* param, void* param_bf16, float* m, float* v, const floa
                   int64_t n, float lr, float beta1, float beta2, float eps, int step,
                   void* stream);
 
+/* ------------------------------------------------------------------------
+ * Relighting with the learned transport: every vertex's values are decoded
+ * by the network on its cluster's support, then relit as by rrt_relight.
+ *   values[v][j] = out(encode(pos_nrm[v]))[j] * scale[cluster[v]][j]
+ *   (0 for a cluster outside [0, C)), then rrt_relight with the transport
+ *   {nvert, nnz = RRT_MLP_OUT, idx = support (per-cluster table),
+ *   val = values (RRT_F32), cluster, nclusters = C}.
+ *   pos_nrm [V][6] float32, cluster [V] int32; radiance [F][V] float32;
+ *   flags as rrt_relight.  The decoded values are bit-identical to
+ *   rrt_mlp_encode + rrt_mlp_forward + the scaling in binary32.
+ *   Workspace: rrt_relight_mlp_workspace() bytes, 256-byte aligned: the
+ *   relight workspace, the decoded values (1 KiB per vertex) and one
+ *   decoding batch of RRT_MLP_BATCH vertices (activations).
+ * --------------------------------------------------------------------- */
+#define RRT_MLP_BATCH 16384
+typedef struct {
+  const void* w;           /* RRT_MLP_WEIGHT_COUNT bfloat16 weights */
+  const float* bias;       /* RRT_MLP_BIAS_COUNT float32 biases */
+  const int32_t* support;  /* [C][RRT_MLP_OUT] flat coefficient indices */
+  const float* scale;      /* [C][RRT_MLP_OUT] per-slot output scales */
+  int nclusters;           /* C >= 1 */
+} rrt_mlp;
+
+int rrt_relight_mlp_workspace(const rrt_light* L, const rrt_rotations* R, int64_t nvert,
+                              size_t* bytes);
+int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M,
+                    const float* pos_nrm, const int32_t* cluster, int64_t nvert,
+                    float* radiance, unsigned flags, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,10 +11,11 @@ import torch
 
 from . import _abi
 from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
-                   RRT_S16, LatLongRotations, Light, RrtError, Rotations, Transport, check, lib)
+                   RRT_S16, LatLongRotations, Light, Mlp, RrtError, Rotations, Transport, check,
+                   lib)
 
 __all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight",
-           "relight_latlong", "mlp_encode",
+           "relight_latlong", "relight_mlp", "mlp_encode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
@@ -249,6 +250,48 @@ def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_sc
                                   RRT_COMPENSATED if compensated else 0,
                                   _dev(workspace, "workspace"), workspace.numel(), _stream()))
     return out
+
+
+def relight_mlp(n, light_idx, light_val, vert_rot, weights, bias, supports, scales, pos_nrm,
+                cluster, frame_rot=None, compensated=False, out=None, workspace=None):
+    """radiance [F, V] float32 with the learned transport (rrt_relight_mlp):
+    weights RRT_MLP_WEIGHT_COUNT bfloat16, bias RRT_MLP_BIAS_COUNT float32,
+    supports [C, 256] int32, scales [C, 256] float32, pos_nrm [V, 6]
+    float32, cluster [V] int32."""
+    L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
+              _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
+              _DTYPES[light_val.dtype])
+    nframes = 1 if frame_rot is None else frame_rot.shape[0]
+    R = Rotations(nframes, _ptr_or_null(frame_rot, "frame_rot", torch.float32).value,
+                  _dev(vert_rot, "vert_rot", torch.float32).value)
+    M = Mlp(_dev(weights, "weights", torch.bfloat16).value, _dev(bias, "bias", torch.float32).value,
+            _dev(supports, "supports", torch.int32).value, _dev(scales, "scales", torch.float32).value,
+            supports.shape[0])
+    nvert = pos_nrm.shape[0]
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), nvert,
+                                        ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _workspace(nbytes.value, pos_nrm.device)
+    if out is None:
+        out = torch.empty((nframes, nvert), dtype=torch.float32, device=pos_nrm.device)
+    check(lib.rrt_relight_mlp(ctypes.byref(L), ctypes.byref(R), ctypes.byref(M),
+                              _dev(pos_nrm, "pos_nrm", torch.float32), _dev(cluster, "cluster", torch.int32),
+                              nvert, _dev(out, "out", torch.float32),
+                              RRT_COMPENSATED if compensated else 0, _dev(workspace, "workspace"),
+                              workspace.numel(), _stream()))
+    return out
+
+
+def relight_mlp_workspace_bytes(n, light_idx, light_val, nvert):
+    L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
+              _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
+              _DTYPES[light_val.dtype])
+    R = Rotations(1, None, None)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), nvert,
+                                        ctypes.byref(nbytes)))
+    return nbytes.value
 
 
 def project_rows(pix, nnz):

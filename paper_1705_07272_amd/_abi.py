@@ -59,6 +59,11 @@ class LatLongRotations(ctypes.Structure):
     _fields_ = [("elev", c_void_p), ("shift", c_void_p)]
 
 
+class Mlp(ctypes.Structure):
+    _fields_ = [("w", c_void_p), ("bias", c_void_p), ("support", c_void_p), ("scale", c_void_p),
+                ("nclusters", c_int)]
+
+
 P = ctypes.POINTER
 
 SIGNATURES = {
@@ -80,6 +85,9 @@ SIGNATURES = {
                             c_size_t, c_void_p]),
     "rrt_relight_prepare": (c_int, [P(Light), c_uint, c_void_p, c_size_t, c_void_p]),
     "rrt_relight_latlong_workspace": (c_int, [P(Light), P(c_size_t)]),
+    "rrt_relight_mlp_workspace": (c_int, [P(Light), P(Rotations), c_int64, P(c_size_t)]),
+    "rrt_relight_mlp": (c_int, [P(Light), P(Rotations), P(Mlp), c_void_p, c_void_p, c_int64,
+                                c_void_p, c_uint, c_void_p, c_size_t, c_void_p]),
     "rrt_relight_latlong": (c_int, [P(Light), P(LatLongRotations), P(Transport), c_void_p, c_uint,
                                     c_void_p, c_size_t, c_void_p]),
     "rrt_relight_prepared": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint,

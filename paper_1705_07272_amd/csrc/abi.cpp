@@ -452,6 +452,101 @@ int rrt_mlp_backward(const void* w, const void* x, int64_t B, const float* dout,
   return launch_mlp_backward(w, x, B, dout, dw, db, ws, static_cast<hipStream_t>(stream));
 }
 
+// Workspace of the learned relight: [relight workspace][values V x 256 f32]
+// [x: one batch, bfloat16 [B][RRT_MLP_IN]][activations of one batch]
+struct RelightMlpWs {
+  size_t relight_total, values_off, x_off, acts_off, acts_bytes, total;
+};
+
+static RelightMlpWs relight_mlp_ws(const rrt_light* L, int64_t nvert) {
+  RelightMlpWs w;
+  w.relight_total = relight_ws(L->n, L->dtype == RRT_F16).total;
+  w.values_off = w.relight_total;
+  w.x_off = w.values_off + align256(size_t(nvert) * RRT_MLP_OUT * sizeof(float));
+  const int64_t B = nvert < RRT_MLP_BATCH ? nvert : RRT_MLP_BATCH;
+  w.acts_off = w.x_off + align256(size_t(B) * RRT_MLP_IN * 2);
+  w.acts_bytes = mlp_workspace_bytes(B);
+  w.total = w.acts_off + align256(w.acts_bytes);
+  return w;
+}
+
+static int validate_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M,
+                                int64_t nvert, rrt_transport* T) {
+  if (!M) return fail(RRT_ERR_INVALID, "relight_mlp: null decoder");
+  if (nvert < 0 || nvert > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "relight_mlp: nvert=%lld out of range", (long long)nvert);
+  if (!M->w || !M->bias || !M->support || !M->scale || M->nclusters < 1)
+    return fail(RRT_ERR_INVALID, "relight_mlp: decoder needs weights, biases, supports, scales and nclusters >= 1");
+  T->nvert = nvert;
+  T->nnz = RRT_MLP_OUT;
+  T->idx = M->support;
+  T->val = nullptr;
+  T->dtype = RRT_F32;
+  T->block_scale = nullptr;
+  T->cluster = nullptr;
+  T->nclusters = M->nclusters;
+  T->brdf = nullptr;
+  T->material = nullptr;
+  T->nmaterials = 0;
+  if (!L) return fail(RRT_ERR_INVALID, "relight_mlp: null lighting");
+  const int st = validate_light(L);
+  if (st) return st;
+  if (RRT_MLP_OUT > int64_t(6) * L->n * L->n)
+    return fail(RRT_ERR_INVALID, "relight_mlp: n=%d has fewer than %d coefficients", L->n, RRT_MLP_OUT);
+  return RRT_OK;
+}
+
+int rrt_relight_mlp_workspace(const rrt_light* L, const rrt_rotations* R, int64_t nvert,
+                              size_t* bytes) {
+  if (!bytes) return fail(RRT_ERR_INVALID, "relight_mlp_workspace: null bytes");
+  (void)R;
+  if (!L) return fail(RRT_ERR_INVALID, "relight_mlp_workspace: null lighting");
+  int st = validate_light(L);
+  if (st) return st;
+  if (nvert < 0 || nvert > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "relight_mlp_workspace: nvert=%lld out of range", (long long)nvert);
+  *bytes = relight_mlp_ws(L, nvert).total;
+  return RRT_OK;
+}
+
+int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M,
+                    const float* pos_nrm, const int32_t* cluster, int64_t nvert,
+                    float* radiance, unsigned flags, void* ws, size_t ws_bytes, void* stream) {
+  rrt_transport T;
+  int st = validate_relight_mlp(L, R, M, nvert, &T);
+  if (st) return st;
+  if (nvert > 0 && (!pos_nrm || !cluster))
+    return fail(RRT_ERR_INVALID, "relight_mlp: null positions/normals or clusters");
+  T.cluster = cluster;
+  // validate everything (the values pointer is a placeholder) before enqueueing anything
+  T.val = pos_nrm;
+  st = validate_relight(L, R, &T);
+  if (st) return st;
+  st = check_relight_flags(L, flags, &T);
+  if (st) return st;
+  const RelightMlpWs w = relight_mlp_ws(L, nvert);
+  st = check_ws(ws, ws_bytes, w.total, "relight_mlp");
+  if (st) return st;
+  if (nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight_mlp: null radiance");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* values = reinterpret_cast<float*>(base + w.values_off);
+  for (int64_t v0 = 0; v0 < nvert; v0 += RRT_MLP_BATCH) {
+    const int64_t B = nvert - v0 < RRT_MLP_BATCH ? nvert - v0 : RRT_MLP_BATCH;
+    if ((st = launch_mlp_encode(pos_nrm + v0 * 6, B, base + w.x_off, s))) return st;
+    if ((st = launch_mlp_forward(M->w, M->bias, base + w.x_off, B, values + v0 * RRT_MLP_OUT,
+                                 base + w.acts_off, s)))
+      return st;
+    if ((st = launch_scale_rows(values + v0 * RRT_MLP_OUT, cluster + v0, M->scale, B,
+                                M->nclusters, s)))
+      return st;
+  }
+  T.val = values;
+  st = rrt_relight_prepare(L, flags, ws, w.relight_total, stream);
+  if (st) return st;
+  return rrt_relight_prepared(L, R, &T, radiance, flags, ws, w.relight_total, stream);
+}
+
 int rrt_mse(const float* out, const float* target, int64_t count, float* dout, double* loss,
             void* stream) {
   if (count < 0 || count > (int64_t(1) << 40)) return fail(RRT_ERR_INVALID, "mse: bad count");

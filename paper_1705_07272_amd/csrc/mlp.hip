@@ -333,6 +333,24 @@ static MlpWs carve(void* ws, int64_t B) {
   return w;
 }
 
+// Decoded values of a batch: the network's outputs times the per-slot scales
+// of each vertex's cluster (0 for a cluster outside [0, C)).
+__global__ void scale_rows_kernel(float* __restrict__ out, const int32_t* __restrict__ cluster,
+                                  const float* __restrict__ scale, int64_t B, int C) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B * RRT_MLP_OUT) return;
+  const int c = cluster[i / RRT_MLP_OUT];
+  out[i] = (c >= 0 && c < C) ? out[i] * scale[int64_t(c) * RRT_MLP_OUT + i % RRT_MLP_OUT] : 0.0f;
+}
+
+int launch_scale_rows(float* out, const int32_t* cluster, const float* scale, int64_t B, int C,
+                      hipStream_t s) {
+  if (B == 0) return RRT_OK;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks(B * RRT_MLP_OUT)), dim3(256), 0, s, out,
+                     cluster, scale, B, C);
+  return check_launch("scale_rows");
+}
+
 int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s) {
   hipLaunchKernelGGL(encode_kernel, dim3(blocks(B * RRT_MLP_IN)), dim3(256), 0, s, in,
                      static_cast<uint16_t*>(out), B);

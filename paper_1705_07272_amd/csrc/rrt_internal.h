@@ -83,6 +83,8 @@ int launch_relight(const RelightLaunch& a, hipStream_t s);
 // Learned decoder (mlp.hip).
 size_t mlp_workspace_bytes(int64_t B);
 int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s);
+int launch_scale_rows(float* out, const int32_t* cluster, const float* scale, int64_t B, int C,
+                      hipStream_t s);
 int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, float* out,
                        void* ws, hipStream_t s);
 int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* dout, float* dw,

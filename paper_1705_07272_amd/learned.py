@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import (RRT_MLP_BIAS_COUNT, RRT_MLP_WEIGHT_COUNT, adam_step, mlp_backward, mlp_encode,
-               mlp_forward, mlp_workspace, mse)
+               mlp_forward, mlp_workspace, mse, relight_mlp)
 
 LAYER_SHAPES = [(256, 128), (256, 256), (256, 256), (256, 256), (256, 256)]
 
@@ -111,6 +111,14 @@ class TransportDecoder:
             mlp_forward(self.w_bf16, self.bias, x, workspace=ws, out=out[s:e])
         out *= self.scales[clusters.to(self.device).long()]
         return out
+
+    def relight(self, n, light_idx, light_val, vert_rot, inputs, clusters, frame_rot=None,
+                out=None, workspace=None):
+        """Decode and relight in one library call (rrt_relight_mlp): radiance
+        [F, V] with each vertex's values decoded on its cluster's support."""
+        return relight_mlp(n, light_idx, light_val, vert_rot, self.w_bf16, self.bias,
+                           self.supports, self.scales, inputs, clusters, frame_rot=frame_rot,
+                           out=out, workspace=workspace)
 
     def parameter_bytes(self):
         """Device bytes of what inference needs: BF16 weights, FP32 biases,

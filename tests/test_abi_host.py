@@ -264,3 +264,32 @@ def test_latlong_validation(rrt):
     assert call(flags=E.RRT_CHAIN_RULE) == E.RRT_ERR_INVALID
     assert call(wsb=64) == E.RRT_ERR_WORKSPACE
     assert call(elev=0) == E.RRT_ERR_INVALID
+
+
+def test_relight_mlp_validation(rrt):
+    """The learned relight checks the decoder, sizes, flags and workspace
+    before anything is enqueued."""
+    E = rrt._abi
+    lib = rrt.lib
+    L = E.Light(16, 10, 8, 8, 0)
+    R = E.Rotations(1, 0, 8)
+    nb = ctypes.c_size_t(0)
+    assert lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), 100,
+                                         ctypes.byref(nb)) == E.RRT_OK
+    assert nb.value > 100 * 256 * 4
+    assert lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), -1,
+                                         ctypes.byref(nb)) == E.RRT_ERR_INVALID
+
+    def call(M, nvert=100, flags=0, wsb=1 << 30, pos=8, clu=8, L=L):
+        return lib.rrt_relight_mlp(ctypes.byref(L), ctypes.byref(R),
+                                   None if M is None else ctypes.byref(M), _p(pos), _p(clu), nvert,
+                                   _p(8), flags, _p(256), wsb, None)
+
+    good = E.Mlp(8, 8, 8, 8, 4)
+    assert call(None) == E.RRT_ERR_INVALID
+    assert call(E.Mlp(8, 8, 8, 8, 0)) == E.RRT_ERR_INVALID
+    assert call(E.Mlp(0, 8, 8, 8, 4)) == E.RRT_ERR_INVALID
+    assert call(good, pos=0) == E.RRT_ERR_INVALID
+    assert call(good, flags=8) == E.RRT_ERR_INVALID
+    assert call(good, wsb=1024) == E.RRT_ERR_WORKSPACE
+    assert call(good, L=E.Light(4, 10, 8, 8, 0)) == E.RRT_ERR_INVALID   # 96 < 256 coefficients
