@@ -22,7 +22,14 @@
 //   * the transport entries are decoded once per vertex into an LDS list; the
 //     entries inside the block read the image, the coarser ones read the FP64
 //     block-sum grid after the levels above the blocks; products are
-//     accumulated per lane and reduced with lane shuffles.
+//     accumulated per lane and reduced with lane shuffles;
+//   * a block that holds no listed entry only contributes its sum to the
+//     levels above it and skips the image, the levels and the entry scan.
+//
+// Variants of the same kernel: the chain rule for the finest level
+// (Sec. V.A-V.B, eq:pde1-eq:pde3), the triple product with a BRDF factor per
+// material (Sec. III, eq:tripleSum), and the longitude-latitude map with its
+// elevation rotation and exact azimuth shifts (Sec. V.A).
 #include <hip/hip_fp16.h>
 
 #include "geometry.h"
