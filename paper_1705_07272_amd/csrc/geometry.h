@@ -162,11 +162,14 @@ __device__ __forceinline__ unsigned source_texel_scaled(int x, int y, int z, int
   const float off = float(1 << (logn - 1)) + eps;
   const float qs = __builtin_fmaf(__builtin_amdgcn_cubesc(fx, fy, fz), hr, off);
   const float qt = __builtin_fmaf(__builtin_amdgcn_cubetc(fx, fy, fz), hr, off);
-  const float es = __builtin_amdgcn_fractf(qs), et = __builtin_amdgcn_fractf(qt);
-  // ((face n + i) n + j) << ES
-  const unsigned face = unsigned(int(__builtin_amdgcn_cubeid(fx, fy, fz)));
-  const unsigned row = (unsigned(int(qs)) << ES) + (face << (2 * logn + ES));
-  unsigned at = unsigned(int(qt)) * (unsigned(1) << (logn + ES)) + row;
+  // q > 0, so truncation is the floor; the flat index (face n + i) n + j is
+  // below 6 * 2^20 < 2^24 and so exact in binary32 arithmetic
+  const float js = __builtin_truncf(qs), it = __builtin_truncf(qt);
+  const float es = qs - js, et = qt - it;
+  const float nf = float(1 << logn);
+  const float flat = __builtin_fmaf(__builtin_amdgcn_cubeid(fx, fy, fz), nf * nf,
+                                    __builtin_fmaf(it, nf, js));
+  unsigned at = unsigned(flat) << ES;
   if (!(fminf(es, et) >= 2.0f * eps)) at = unsigned(source_texel_exact(x, y, z, logn)) << ES;
   return at;
 }
