@@ -535,7 +535,7 @@ int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M
     const int64_t B = nvert - v0 < RRT_MLP_BATCH ? nvert - v0 : RRT_MLP_BATCH;
     if ((st = launch_mlp_encode(pos_nrm + v0 * 6, B, base + w.x_off, s))) return st;
     if ((st = launch_mlp_forward(M->w, M->bias, base + w.x_off, B, values + v0 * RRT_MLP_OUT,
-                                 base + w.acts_off, s)))
+                                 base + w.acts_off, s, /*keep_z=*/false)))
       return st;
     if ((st = launch_scale_rows(values + v0 * RRT_MLP_OUT, cluster + v0, M->scale, B,
                                 M->nclusters, s)))

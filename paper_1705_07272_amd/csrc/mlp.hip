@@ -55,7 +55,8 @@ enum Epilogue {
   kEpiHidden = 0,   // z = acc + bias -> store z (FP32) and gelu(z) (BF16)
   kEpiOutput = 1,   // out = acc + bias -> FP32
   kEpiGeluGrad = 2, // dz = acc * gelu'(zprev) -> BF16
-  kEpiPlain = 3     // acc -> FP32
+  kEpiPlain = 3,    // acc -> FP32
+  kEpiHiddenInfer = 4  // gelu(acc + bias) -> BF16 only (inference: no z kept)
 };
 
 struct GemmArgs {
@@ -170,6 +171,8 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
           x += g.bias[n];
           g.out_f32[at] = x;
           g.out_bf16[at] = bf16_bits(gelu_f(x));
+        } else if (EPI == kEpiHiddenInfer) {
+          g.out_bf16[at] = bf16_bits(gelu_f(x + g.bias[n]));
         } else if (EPI == kEpiOutput) {
           g.out_f32[at] = x + g.bias[n];
         } else if (EPI == kEpiGeluGrad) {
@@ -358,7 +361,7 @@ int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s) {
 }
 
 int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, float* out,
-                       void* ws, hipStream_t s) {
+                       void* ws, hipStream_t s, bool keep_z) {
   const uint16_t* W = static_cast<const uint16_t*>(w);
   MlpWs k = carve(ws, B);
   const uint16_t* a_in = static_cast<const uint16_t*>(x);
@@ -372,9 +375,13 @@ int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, 
     g.bias = b + mlp_bias_offset(l);
     int st;
     if (l < RRT_MLP_WEIGHTS - 1) {
-      g.out_f32 = k.z[l];
       g.out_bf16 = k.a[l];
-      st = gemm<false, true, kEpiHidden>(g, s);
+      if (keep_z) {
+        g.out_f32 = k.z[l];
+        st = gemm<false, true, kEpiHidden>(g, s);
+      } else {
+        st = gemm<false, true, kEpiHiddenInfer>(g, s);
+      }
       a_in = k.a[l];
     } else {
       g.out_f32 = out;

@@ -86,7 +86,8 @@ int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s);
 int launch_scale_rows(float* out, const int32_t* cluster, const float* scale, int64_t B, int C,
                       hipStream_t s);
 int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, float* out,
-                       void* ws, hipStream_t s);
+                       void* ws, hipStream_t s,
+                       bool keep_z = true);
 int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* dout, float* dw,
                         float* db, void* ws, hipStream_t s);
 int launch_mse(const float* out, const float* tgt, int64_t count, float* dout, double* loss,
