@@ -71,17 +71,28 @@ def haar_inverse(coef, out=None):
     return out
 
 
-def topk(x, k):
-    """Row-wise k largest |x| -> (idx int32 ascending, values) for x [rows, len]."""
+def topk(x, k, out=None, workspace=None):
+    """Row-wise k largest |x| -> (idx int32 ascending, values) for x [rows, len].
+    out: optional (idx, val) tensors to fill; workspace: optional device
+    buffer of at least rrt_topk_workspace() bytes."""
     rows, length = x.shape
-    idx = torch.empty((rows, k), dtype=torch.int32, device=x.device)
-    val = torch.empty((rows, k), dtype=torch.float32, device=x.device)
+    if out is None:
+        idx = torch.empty((rows, k), dtype=torch.int32, device=x.device)
+        val = torch.empty((rows, k), dtype=torch.float32, device=x.device)
+    else:
+        idx, val = out
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_topk_workspace(rows, length, k, ctypes.byref(nbytes)))
-    ws = _workspace(nbytes.value, x.device)
-    check(lib.rrt_topk(_dev(x, "x", torch.float32), rows, length, k, _dev(idx, "idx"),
-                       _dev(val, "val"), _dev(ws, "ws"), nbytes.value, _stream()))
+    ws = _workspace(nbytes.value, x.device) if workspace is None else workspace
+    check(lib.rrt_topk(_dev(x, "x", torch.float32), rows, length, k, _dev(idx, "idx", torch.int32),
+                       _dev(val, "val", torch.float32), _dev(ws, "ws"), ws.numel(), _stream()))
     return idx, val
+
+
+def topk_workspace_bytes(rows, length, k):
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_topk_workspace(rows, length, k, ctypes.byref(nbytes)))
+    return nbytes.value
 
 
 def coarsen_indices(idx, n, levels):
