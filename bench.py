@@ -463,6 +463,10 @@ def main():
     lis = [torch.empty((1, K), dtype=torch.int32, device="cuda") for _ in range(slots)]
     lvs = [torch.empty((1, K), dtype=torch.float32, device="cuda") for _ in range(slots)]
     keep = [None] * slots          # what the relight of a slot reads, alive until reuse
+    # heavy-first processing order, recomputed from the rows in every step
+    orders = [torch.empty(V, dtype=torch.int32, device="cuda") for _ in range(slots)]
+    ord_ws = [torch.empty(rrt.relight_order_workspace_bytes(V), dtype=torch.uint8, device="cuda")
+              for _ in range(slots)]
     prep_done = [torch.cuda.Event() for _ in range(slots)]
     rel_done = [torch.cuda.Event() for _ in range(slots)]
     counter = [0]
@@ -482,6 +486,8 @@ def main():
                 li = rrt.coarsen_indices(li, n, L)
             prep = rrt.prepare_lighting(n_rot, li[0], lv[0], workspace=wss[slot],  # a3
                                         chain_rule=args.chain_rule)
+            order = rrt.relight_order(n_rot, inp["idx"], out=orders[slot],
+                                      workspace=ord_ws[slot])
             keep[slot] = prep
             if ev is not None:
                 ev[3].record(side)
@@ -491,7 +497,7 @@ def main():
             ev[0].record(main)
         rrt.relight_prepared(prep, inp["rot"], inp["idx"], inp["val"], frame_rot=inp["frot"],
                              block_scale=inp["scale"], compensated=light_f16, out=out,
-                             brdf=inp["brdf"], material=inp["material"])
+                             brdf=inp["brdf"], material=inp["material"], order=order)
         if ev is not None:
             ev[1].record(main)
         rel_done[slot].record(main)

@@ -173,6 +173,11 @@ typedef struct {
                                [V] row of each vertex; rows outside [0, M)
                                give radiance 0 */
   int nmaterials;           /* M >= 1 when brdf != NULL */
+  const int32_t* order;     /* NULL (vertices in index order) or [V] a
+                               permutation of 0..V-1: the order in which the
+                               vertices are processed (e.g. rrt_relight_order);
+                               results do not depend on it, only the time
+                               does; entries outside [0, V) are skipped */
 } rrt_transport;
 
 typedef struct {
@@ -195,6 +200,16 @@ int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_
    rrt_relight_prepare followed by rrt_relight_prepared. */
 int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
                 float* radiance, unsigned flags, void* ws, size_t ws_bytes, void* stream);
+
+/* Processing order for rrt_relight: the vertices sorted by the number of
+   cube faces their rows touch, most first (a vertex's work grows with it),
+   so that the expensive vertices do not start last.  Within a face count
+   the order is unspecified.  Reads T->idx (or T->cluster's support rows);
+   dense rows (idx NULL) give the index order.  order [V] int32.
+   Workspace: rrt_relight_order_workspace() bytes (256-byte aligned). */
+int rrt_relight_order_workspace(int64_t nvert, size_t* bytes);
+int rrt_relight_order(const rrt_light* L, const rrt_transport* T, int32_t* order, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* The two halves of rrt_relight, for relighting many vertex batches or
    frame sets under one lighting:

@@ -15,7 +15,7 @@ from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M
                    lib)
 
 __all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight",
-           "relight_latlong", "relight_mlp", "mlp_encode",
+           "relight_latlong", "relight_mlp", "relight_order", "mlp_encode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
@@ -119,7 +119,7 @@ def haar_phase_shift(coef, rot):
 
 
 def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
-                 cluster=None, brdf=None, material=None):
+                 cluster=None, brdf=None, material=None, order=None):
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -137,7 +137,8 @@ def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, blo
                   0 if cluster is None else t_idx.shape[0],
                   _ptr_or_null(brdf, "brdf", torch.float32).value,
                   _ptr_or_null(material, "material", torch.int32).value,
-                  0 if brdf is None else brdf.shape[0])
+                  0 if brdf is None else brdf.shape[0],
+                  _ptr_or_null(order, "order", torch.int32).value)
     return L, R, T
 
 
@@ -156,7 +157,7 @@ def relight_workspace_bytes(n, light_idx, light_val, vert_rot, t_idx, t_val, fra
 
 def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
             compensated=False, out=None, workspace=None, cluster=None, chain_rule=False,
-            brdf=None, material=None):
+            brdf=None, material=None, order=None):
     """radiance [F, V] float32.
 
     light_idx [k] int32, light_val [k] float32|float16; vert_rot [V, 3, 3]
@@ -169,9 +170,10 @@ def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, blo
     brdf [M, 6, n, n] float32 (texel-domain BRDF x cosine x solid angle in the
     local frame) with material [V] int32 or None: the triple product, t_* then
     hold the visibility rows.
+    order [V] int32: processing order of the vertices (relight_order), or None.
     """
     L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
-                           cluster, brdf, material)
+                           cluster, brdf, material, order)
     flags = _flags(compensated, chain_rule)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
@@ -216,11 +218,12 @@ def prepare_lighting(n, light_idx, light_val, workspace=None, chain_rule=False):
 
 
 def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=None,
-                     compensated=False, out=None, cluster=None, brdf=None, material=None):
+                     compensated=False, out=None, cluster=None, brdf=None, material=None,
+                     order=None):
     """relight() with a lighting already reconstructed by prepare_lighting()
     (the chain rule applies when the lighting was prepared for it)."""
     L, R, T = _descriptors(prep.n, prep.light_idx, prep.light_val, vert_rot, t_idx, t_val,
-                           frame_rot, block_scale, cluster, brdf, material)
+                           frame_rot, block_scale, cluster, brdf, material, order)
     if out is None:
         out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
     check(lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
@@ -302,6 +305,37 @@ def relight_mlp_workspace_bytes(n, light_idx, light_val, nvert):
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), nvert,
                                         ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def relight_order(n, t_idx, cluster=None, out=None, workspace=None, nvert=None, device="cuda"):
+    """Heavy-first processing order [V] int32 of transport rows t_idx [V, nnz]
+    (or, with cluster [V], support rows t_idx [C, nnz]) over 6 n^2
+    coefficients (rrt_relight_order); t_idx None means nvert dense rows."""
+    if t_idx is None:
+        V, nnz, dev_ = nvert, 6 * n * n, torch.device(device)
+    else:
+        V = t_idx.shape[0] if cluster is None else cluster.shape[0]
+        nnz, dev_ = t_idx.shape[-1], t_idx.device
+    dummy = torch.empty(1, dtype=torch.int32, device=dev_)
+    L = Light(n, 1, dummy.data_ptr(), dummy.data_ptr(), RRT_F32)
+    T = Transport(V, nnz, _ptr_or_null(t_idx, "t_idx", torch.int32).value, None, RRT_F32, None,
+                  _ptr_or_null(cluster, "cluster", torch.int32).value,
+                  0 if cluster is None else t_idx.shape[0], None, None, 0, None)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_order_workspace(V, ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = _workspace(nbytes.value, dev_)
+    if out is None:
+        out = torch.empty(V, dtype=torch.int32, device=dev_)
+    check(lib.rrt_relight_order(ctypes.byref(L), ctypes.byref(T), _dev(out, "order", torch.int32),
+                                _dev(workspace, "workspace"), workspace.numel(), _stream()))
+    return out
+
+
+def relight_order_workspace_bytes(nvert):
+    nbytes = ctypes.c_size_t(0)
+    check(lib.rrt_relight_order_workspace(nvert, ctypes.byref(nbytes)))
     return nbytes.value
 
 

@@ -48,7 +48,7 @@ class Transport(ctypes.Structure):
     _fields_ = [("nvert", c_int64), ("nnz", c_int), ("idx", c_void_p), ("val", c_void_p),
                 ("dtype", c_int), ("block_scale", c_void_p), ("cluster", c_void_p),
                 ("nclusters", c_int), ("brdf", c_void_p), ("material", c_void_p),
-                ("nmaterials", c_int)]
+                ("nmaterials", c_int), ("order", c_void_p)]
 
 
 class Rotations(ctypes.Structure):
@@ -85,6 +85,8 @@ SIGNATURES = {
                             c_size_t, c_void_p]),
     "rrt_relight_prepare": (c_int, [P(Light), c_uint, c_void_p, c_size_t, c_void_p]),
     "rrt_relight_latlong_workspace": (c_int, [P(Light), P(c_size_t)]),
+    "rrt_relight_order_workspace": (c_int, [c_int64, P(c_size_t)]),
+    "rrt_relight_order": (c_int, [P(Light), P(Transport), c_void_p, c_void_p, c_size_t, c_void_p]),
     "rrt_relight_mlp_workspace": (c_int, [P(Light), P(Rotations), c_int64, P(c_size_t)]),
     "rrt_relight_mlp": (c_int, [P(Light), P(Rotations), P(Mlp), c_void_p, c_void_p, c_int64,
                                 c_void_p, c_uint, c_void_p, c_size_t, c_void_p]),

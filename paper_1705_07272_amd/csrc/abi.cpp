@@ -279,7 +279,35 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
   a.brdf = T->brdf;
   a.material = T->brdf ? T->material : nullptr;
   a.nmaterials = T->brdf ? T->nmaterials : 0;
+  a.order = T->order;
   return launch_relight(a, static_cast<hipStream_t>(stream));
+}
+
+int rrt_relight_order_workspace(int64_t nvert, size_t* bytes) {
+  if (!bytes) return fail(RRT_ERR_INVALID, "relight_order_workspace: null bytes");
+  if (nvert < 0 || nvert > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "relight_order_workspace: nvert=%lld out of range", (long long)nvert);
+  *bytes = relight_order_workspace_bytes(nvert);
+  return RRT_OK;
+}
+
+int rrt_relight_order(const rrt_light* L, const rrt_transport* T, int32_t* order, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!L || !T) return fail(RRT_ERR_INVALID, "relight_order: null descriptor");
+  if (!valid_n(L->n, 2)) return fail(RRT_ERR_INVALID, "relight_order: n=%d not a power of two in [2,1024]", L->n);
+  if (T->nvert < 0 || T->nvert > int64_t(0x7fffffff))
+    return fail(RRT_ERR_INVALID, "relight_order: nvert=%lld out of range", (long long)T->nvert);
+  if (T->nvert == 0) return RRT_OK;
+  if (!order) return fail(RRT_ERR_INVALID, "relight_order: null order");
+  if (T->nnz < 1) return fail(RRT_ERR_INVALID, "relight_order: nnz=%d < 1", T->nnz);
+  if (T->cluster && (T->nclusters < 1 || !T->idx))
+    return fail(RRT_ERR_INVALID, "relight_order: per-cluster supports need nclusters >= 1 and an idx table");
+  int st = check_ws(ws, ws_bytes, relight_order_workspace_bytes(T->nvert), "relight_order");
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!T->idx) return launch_iota(order, T->nvert, s);   // dense rows: every vertex alike
+  return launch_relight_order(T->idx, T->cluster, T->nclusters, T->nnz, T->nvert, L->n, order,
+                              ws, s);
 }
 
 int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T, float* radiance,
@@ -394,6 +422,7 @@ int rrt_relight_latlong(const rrt_light* L, const rrt_latlong_rotations* R, cons
   a.material = nullptr;
   a.nmaterials = 0;
   a.latlong = true;
+  a.order = T->order;
   a.ll_elev = R->elev;
   a.ll_shift = R->shift;
   a.ll_grid = grid;
@@ -488,6 +517,7 @@ static int validate_relight_mlp(const rrt_light* L, const rrt_rotations* R, cons
   T->brdf = nullptr;
   T->material = nullptr;
   T->nmaterials = 0;
+  T->order = nullptr;
   if (!L) return fail(RRT_ERR_INVALID, "relight_mlp: null lighting");
   const int st = validate_light(L);
   if (st) return st;

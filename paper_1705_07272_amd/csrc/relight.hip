@@ -193,6 +193,7 @@ struct RelightParams {
   int nmat;
   const float* ll_elev;     // lat-long: [V][2] (cos b, sin b)
   const int32_t* ll_shift;  // lat-long: [V][2] (s_a, s_c)
+  const int32_t* order;     // [V] processing order, or NULL
   const float* ll_grid;     // lat-long: the rule's binary32 tables (7 H floats)
   int ll_tab_off;           // lat-long: byte offset of the tables in LDS
 };
@@ -414,7 +415,8 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
 
   const int lane = threadIdx.x;
-  const int64_t v = blockIdx.x;
+  const int64_t v = p.order ? int64_t(p.order[blockIdx.x]) : int64_t(blockIdx.x);
+  if (v < 0 || v >= p.nvert) return;  // not a permutation entry: skipped (uniform)
   const int logn = p.logn;
   const int n = 1 << logn;
   const int G = n >> LOGQ;  // blocks per face side
@@ -848,6 +850,82 @@ __global__ void latlong_grid_kernel(int H, float* __restrict__ grid) {
   }
 }
 
+// Heavy-first order, pass 1 (one wave per vertex): the number of faces the
+// vertex's row touches.
+__global__ __launch_bounds__(kThreads) void order_faces_kernel(
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ cluster, int nclusters,
+    int nnz, int logn, unsigned char* __restrict__ faces) {
+  const int64_t v = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int32_t* row = nullptr;
+  if (cluster) {
+    const int c = cluster[v];
+    if (c >= 0 && c < nclusters) row = idx + int64_t(c) * nnz;
+  } else {
+    row = idx + v * nnz;
+  }
+  unsigned m = 0;
+  if (row) {
+    for (int e = lane; e < nnz; e += kThreads) {
+      const int i = row[e];
+      if (i >= 0 && i < 6 * (1 << (2 * logn))) m |= 1u << (i >> (2 * logn));
+    }
+  }
+  int nf = 0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) nf += __ballot((m >> f) & 1u) ? 1 : 0;
+  if (lane == 0) faces[v] = static_cast<unsigned char>(nf);
+}
+
+// Pass 2 (256 vertices per block): vertex count of every bucket 6 - faces,
+// an LDS histogram per block and one global add per block and bucket.
+__global__ __launch_bounds__(256) void order_hist_kernel(const unsigned char* __restrict__ faces,
+                                                         int64_t nvert,
+                                                         unsigned* __restrict__ counts) {
+  __shared__ unsigned h[7];
+  if (threadIdx.x < 7) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < nvert) atomicAdd(&h[6 - faces[v]], 1u);
+  __syncthreads();
+  if (threadIdx.x < 7 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+// Pass 3 (256 vertices per block): each block reserves a range of every
+// bucket with one global add, then places its vertices in it (the order
+// inside a bucket does not affect any result).
+__global__ __launch_bounds__(256) void order_place_kernel(const unsigned char* __restrict__ faces,
+                                                          int64_t nvert,
+                                                          unsigned* __restrict__ counts,
+                                                          int32_t* __restrict__ order) {
+  __shared__ unsigned h[7], base[7], cur[7];
+  if (threadIdx.x < 7) {
+    h[threadIdx.x] = 0u;
+    cur[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int b = v < nvert ? 6 - faces[v] : -1;
+  if (b >= 0) atomicAdd(&h[b], 1u);
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    unsigned off = 0;
+    for (int k = 0; k < int(threadIdx.x); ++k) off += counts[k];
+    base[threadIdx.x] = off + (h[threadIdx.x] ? atomicAdd(&counts[7 + threadIdx.x], h[threadIdx.x]) : 0u);
+  }
+  __syncthreads();
+  if (b >= 0) order[base[b] + atomicAdd(&cur[b], 1u)] = int32_t(v);
+}
+
+__global__ void iota_kernel(int32_t* __restrict__ out, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = int32_t(i);
+}
+
+__global__ void order_clear_kernel(unsigned* __restrict__ counts) {
+  if (threadIdx.x < 14) counts[threadIdx.x] = 0u;
+}
+
 // Index of coefficient idx at resolution n in the map n >> levels, or -1 for
 // the `levels` finest levels (Mallat layout: the coarse levels are the
 // top-left corner of each face).
@@ -968,6 +1046,7 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   p.ll_shift = a.ll_shift;
   p.ll_grid = a.ll_grid;
   p.ll_tab_off = 0;
+  p.order = a.order;
   const bool chain = (a.flags & RRT_CHAIN_RULE) != 0;
   return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, chain, a.latlong, s)
                    : launch_src<float>(p, a.n, a.nvert, chain, a.latlong, s);
@@ -996,6 +1075,36 @@ int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStr
                        reinterpret_cast<float4*>(blocks));
   }
   return check_launch("source_blocks");
+}
+
+int launch_iota(int32_t* out, int64_t count, hipStream_t s) {
+  if (count == 0) return RRT_OK;
+  hipLaunchKernelGGL(iota_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, out, count);
+  return check_launch("iota");
+}
+
+size_t relight_order_workspace_bytes(int64_t nvert) {
+  return ((size_t(nvert) + 255) & ~size_t(255)) + 256;
+}
+
+int launch_relight_order(const int32_t* idx, const int32_t* cluster, int nclusters, int nnz,
+                         int64_t nvert, int n, int32_t* order, void* ws, hipStream_t s) {
+  if (nvert == 0) return RRT_OK;
+  unsigned char* faces = static_cast<unsigned char*>(ws);
+  unsigned* counts =
+      reinterpret_cast<unsigned*>(faces + ((size_t(nvert) + 255) & ~size_t(255)));
+  hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(64), 0, s, counts);
+  int st = check_launch("order_clear");
+  if (st) return st;
+  hipLaunchKernelGGL(order_faces_kernel, dim3(unsigned(nvert)), dim3(kThreads), 0, s, idx,
+                     cluster, nclusters, nnz, ilog2(n), faces);
+  if ((st = check_launch("order_faces"))) return st;
+  const unsigned blocks = unsigned((nvert + 255) / 256);
+  hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, faces, nvert, counts);
+  if ((st = check_launch("order_hist"))) return st;
+  hipLaunchKernelGGL(order_place_kernel, dim3(blocks), dim3(256), 0, s, faces, nvert, counts,
+                     order);
+  return check_launch("order_place");
 }
 
 int launch_latlong_grid(int H, float* grid, hipStream_t s) {

@@ -65,6 +65,7 @@ struct RelightLaunch {
   const float* brdf;        // triple product: [M][6 n^2] texel factor, or NULL
   const int32_t* material;  // [V] row of brdf, or NULL (row 0)
   int nmaterials;
+  const int32_t* order = nullptr;    // [V] processing order, or nullptr
   // longitude-latitude map (then vert_rot, frame_rot, cluster, brdf unused, nframes = 1)
   bool latlong = false;
   const float* ll_elev = nullptr;    // [V][2] (cos b, sin b)
@@ -79,6 +80,11 @@ int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStr
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
                            hipStream_t s);
 int launch_relight(const RelightLaunch& a, hipStream_t s);
+// Heavy-first processing order (faces touched by each row, most first).
+size_t relight_order_workspace_bytes(int64_t nvert);
+int launch_iota(int32_t* out, int64_t count, hipStream_t s);
+int launch_relight_order(const int32_t* idx, const int32_t* cluster, int nclusters, int nnz,
+                         int64_t nvert, int n, int32_t* order, void* ws, hipStream_t s);
 
 // Learned decoder (mlp.hip).
 size_t mlp_workspace_bytes(int64_t B);

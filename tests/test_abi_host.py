@@ -293,3 +293,22 @@ def test_relight_mlp_validation(rrt):
     assert call(good, flags=8) == E.RRT_ERR_INVALID
     assert call(good, wsb=1024) == E.RRT_ERR_WORKSPACE
     assert call(good, L=E.Light(4, 10, 8, 8, 0)) == E.RRT_ERR_INVALID   # 96 < 256 coefficients
+
+
+def test_relight_order_validation(rrt):
+    E = rrt._abi
+    lib = rrt.lib
+    nb = ctypes.c_size_t(0)
+    assert lib.rrt_relight_order_workspace(1000, ctypes.byref(nb)) == E.RRT_OK and nb.value >= 1000
+    assert lib.rrt_relight_order_workspace(-1, ctypes.byref(nb)) == E.RRT_ERR_INVALID
+    L = E.Light(16, 1, 8, 8, 0)
+    T = E.Transport(100, 16, 8, 8, 0, 0, 0, 0, 0, 0, 0, 0)
+    assert lib.rrt_relight_order(ctypes.byref(L), ctypes.byref(T), _p(0), _p(256), 1 << 20,
+                                 None) == E.RRT_ERR_INVALID                  # null order
+    assert lib.rrt_relight_order(ctypes.byref(L), ctypes.byref(T), _p(8), _p(256), 16,
+                                 None) == E.RRT_ERR_WORKSPACE
+    assert lib.rrt_relight_order(ctypes.byref(E.Light(12, 1, 8, 8, 0)), ctypes.byref(T), _p(8),
+                                 _p(256), 1 << 20, None) == E.RRT_ERR_INVALID
+    empty = E.Transport(0, 16, 8, 8, 0, 0, 0, 0, 0, 0, 0, 0)
+    assert lib.rrt_relight_order(ctypes.byref(L), ctypes.byref(empty), _p(0), _p(0), 0,
+                                 None) == E.RRT_OK

@@ -646,3 +646,40 @@ def test_latlong_with_s16_transport(rrt):
     ref = relight_latlong(case["light_idx"], case["light_val"], H, case["elev"], case["shift"],
                           case["t_idx"], decoded, return_scale=True)
     check_frames(out, ref)
+
+
+# ---------------------------------------------------------------- processing order
+def test_relight_order_heavy_first_and_results_unchanged(rrt):
+    """rrt_relight_order is a permutation sorting the vertices by the faces
+    their rows touch, most first; relighting in that order, in reverse or
+    in a random order gives the index-order result bit for bit; entries
+    outside [0, V) are skipped (those vertices keep what out held)."""
+    from cases import build_case, workload
+    w = workload(980, 32, 1024, 257, 256, exp_lo=1.0, exp_hi=30.0)
+    case = build_case(w)
+    order = rrt.relight_order(32, dev(case["t_idx"])).cpu().numpy()
+    V = case["t_idx"].shape[0]
+    assert np.array_equal(np.sort(order), np.arange(V))
+    faces = np.array([len(np.unique(r[(r >= 0) & (r < 6 * 32 * 32)] // (32 * 32)))
+                      for r in case["t_idx"]])
+    assert np.all(np.diff(faces[order]) <= 0) and faces.max() > faces.min()
+    base = run_relight(rrt, case)
+    rng = np.random.default_rng(3)
+    for o in (order, order[::-1].copy(), rng.permutation(V).astype(np.int32)):
+        assert np.array_equal(run_relight(rrt, case, order=dev(o.astype(np.int32))), base)
+    partial = order.copy()
+    partial[[0, 5]] = [-1, V]
+    out = torch.full((1, V), float("nan"), device="cuda")
+    got = run_relight(rrt, case, order=dev(partial), out=out)
+    skipped = order[[0, 5]]
+    keep = np.setdiff1d(np.arange(V), skipped)
+    assert np.all(np.isnan(got[0, skipped])) and np.array_equal(got[0, keep], base[0, keep])
+    # dense rows: every vertex alike, the index order
+    dense = rrt.relight_order(4, None, nvert=7)
+    assert np.array_equal(dense.cpu().numpy(), np.arange(7))
+    # cluster support rows: the order follows each vertex's cluster row
+    cl = np.array([1, 0, 1, 2, 0], np.int32)
+    sup = case["t_idx"][[int(np.argmax(faces)), int(np.argmin(faces)), 7]]
+    co = rrt.relight_order(32, dev(sup), cluster=dev(cl)).cpu().numpy()
+    fs = np.array([faces[int(np.argmax(faces))], faces[int(np.argmin(faces))], faces[7]])[cl]
+    assert np.array_equal(np.sort(co), np.arange(5)) and np.all(np.diff(fs[co]) <= 0)
