@@ -251,12 +251,17 @@ __global__ __launch_bounds__(kChunkThreads) void tk_hist(const float* __restrict
   for (int b = tid; b < kBins; b += kChunkThreads) out[b] = h[b];
 }
 
-__global__ __launch_bounds__(kRowThreads) void tk_bin(const uint32_t* __restrict__ hist,
-                                                      int chunks, int k,
-                                                      uint32_t* __restrict__ eq_base,
-                                                      uint32_t* __restrict__ par) {
-  constexpr int kWaves = kRowThreads / 64;
-  constexpr int kPer = kBins / kRowThreads;
+// The single-workgroup steps of a long row run with kSmallThreads so that
+// they find room on a CU next to other work (a 1024-thread workgroup needs
+// 16 free wave slots on one CU at once).
+constexpr int kSmallThreads = 256;
+
+__global__ __launch_bounds__(kSmallThreads) void tk_bin(const uint32_t* __restrict__ hist,
+                                                        int chunks, int k,
+                                                        uint32_t* __restrict__ eq_base,
+                                                        uint32_t* __restrict__ par) {
+  constexpr int kWaves = kSmallThreads / 64;
+  constexpr int kPer = kBins / kSmallThreads;
   __shared__ int sh[kWaves];
   __shared__ int s_bin, s_need;
   const int tid = threadIdx.x, row = blockIdx.x;
@@ -359,11 +364,11 @@ __global__ __launch_bounds__(kChunkThreads) void tk_cand(const float* __restrict
       });
 }
 
-__global__ __launch_bounds__(kRowThreads) void tk_resolve(int64_t len,
-                                                          const uint32_t* __restrict__ ckey,
-                                                          const int32_t* __restrict__ cidx,
-                                                          uint32_t* __restrict__ par) {
-  constexpr int kWaves = kRowThreads / 64;
+__global__ __launch_bounds__(kSmallThreads) void tk_resolve(int64_t len,
+                                                            const uint32_t* __restrict__ ckey,
+                                                            const int32_t* __restrict__ cidx,
+                                                            uint32_t* __restrict__ par) {
+  constexpr int kWaves = kSmallThreads / 64;
   __shared__ unsigned h[1024];
   __shared__ int sh[kWaves];
   __shared__ unsigned s_prefix, s_need;
@@ -384,21 +389,28 @@ __global__ __launch_bounds__(kRowThreads) void tk_resolve(int64_t len,
       s_prefix = prefix;
       s_need = need;
     }
-    h[tid] = 0;
+    for (int b = tid; b < nb; b += kSmallThreads) h[b] = 0;
     __syncthreads();
-    for (int i = tid; i < m; i += kRowThreads) {
+    for (int i = tid; i < m; i += kSmallThreads) {
       const unsigned u = kk[i];
       if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & unsigned(nb - 1)], 1u);
     }
     __syncthreads();
-    // bin b = tid: keys above it, from the top
-    const int mine = tid < nb ? int(h[tid]) : 0;
+    // bins per * tid .. per * tid + per - 1 of this thread: keys above them,
+    // then each bin from the top
+    const int per = nb / kSmallThreads;
+    int mine = 0;
+    for (int j = 0; j < per; ++j) mine += int(h[per * tid + j]);
     int total;
     const int before = block_scan<kWaves>(mine, &total, sh);
-    const unsigned above = unsigned(total - before - mine);
-    if (tid < nb && above < need && above + unsigned(mine) >= need) {
-      s_prefix = prefix | (unsigned(tid) << shift);
-      s_need = need - above;
+    unsigned above = unsigned(total - before - mine);
+    for (int j = per - 1; j >= 0; --j) {
+      const unsigned c = h[per * tid + j];
+      if (above < need && above + c >= need) {
+        s_prefix = prefix | (unsigned(per * tid + j) << shift);
+        s_need = need - above;
+      }
+      above += c;
     }
     __syncthreads();
     prefix = s_prefix;
@@ -410,7 +422,7 @@ __global__ __launch_bounds__(kRowThreads) void tk_resolve(int64_t len,
   if (tid == 0) s_cut = -1;
   __syncthreads();
   int base = 0;
-  for (int c0 = 0; c0 < m && base < int(need); c0 += kRowThreads) {
+  for (int c0 = 0; c0 < m && base < int(need); c0 += kSmallThreads) {
     const int i = c0 + tid;
     const int eq = (i < m && kk[i] == prefix) ? 1 : 0;
     int total;
@@ -496,11 +508,11 @@ int launch_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, 
     const dim3 grid(unsigned(cp.chunks), unsigned(rows));
     hipLaunchKernelGGL(tk_hist, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
                        w.hist);
-    hipLaunchKernelGGL(tk_bin, dim3(unsigned(rows)), dim3(kRowThreads), 0, s, w.hist, cp.chunks, k,
+    hipLaunchKernelGGL(tk_bin, dim3(unsigned(rows)), dim3(kSmallThreads), 0, s, w.hist, cp.chunks, k,
                        w.eq_base, w.par);
     hipLaunchKernelGGL(tk_cand, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
                        w.eq_base, w.par, w.ckey, w.cidx);
-    hipLaunchKernelGGL(tk_resolve, dim3(unsigned(rows)), dim3(kRowThreads), 0, s, len, w.ckey,
+    hipLaunchKernelGGL(tk_resolve, dim3(unsigned(rows)), dim3(kSmallThreads), 0, s, len, w.ckey,
                        w.cidx, w.par);
     hipLaunchKernelGGL(tk_count, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
                        w.par, w.sel_cnt);
