@@ -346,10 +346,13 @@ int rrt_adam_step(float* param, void* param_bf16, float* m, float* v, const floa
  *   val = values (RRT_F32), cluster, nclusters = C}.
  *   pos_nrm [V][6] float32, cluster [V] int32; radiance [F][V] float32;
  *   flags as rrt_relight.  The decoded values are bit-identical to
- *   rrt_mlp_encode + rrt_mlp_forward + the scaling in binary32.
+ *   rrt_mlp_encode + rrt_mlp_forward + the scaling in binary32; the
+ *   vertices are relit in the rrt_relight_order order of their cluster
+ *   rows (results unchanged).
  *   Workspace: rrt_relight_mlp_workspace() bytes, 256-byte aligned: the
- *   relight workspace, the decoded values (1 KiB per vertex) and one
- *   decoding batch of RRT_MLP_BATCH vertices (activations).
+ *   relight workspace, the decoded values (1 KiB per vertex), one
+ *   decoding batch of RRT_MLP_BATCH vertices (activations) and the order
+ *   (4 bytes per vertex plus its workspace).
  * --------------------------------------------------------------------- */
 #define RRT_MLP_BATCH 16384
 typedef struct {

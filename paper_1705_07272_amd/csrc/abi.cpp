@@ -484,7 +484,7 @@ int rrt_mlp_backward(const void* w, const void* x, int64_t B, const float* dout,
 // Workspace of the learned relight: [relight workspace][values V x 256 f32]
 // [x: one batch, bfloat16 [B][RRT_MLP_IN]][activations of one batch]
 struct RelightMlpWs {
-  size_t relight_total, values_off, x_off, acts_off, acts_bytes, total;
+  size_t relight_total, values_off, x_off, acts_off, acts_bytes, order_off, order_ws_off, total;
 };
 
 static RelightMlpWs relight_mlp_ws(const rrt_light* L, int64_t nvert) {
@@ -495,7 +495,9 @@ static RelightMlpWs relight_mlp_ws(const rrt_light* L, int64_t nvert) {
   const int64_t B = nvert < RRT_MLP_BATCH ? nvert : RRT_MLP_BATCH;
   w.acts_off = w.x_off + align256(size_t(B) * RRT_MLP_IN * 2);
   w.acts_bytes = mlp_workspace_bytes(B);
-  w.total = w.acts_off + align256(w.acts_bytes);
+  w.order_off = w.acts_off + align256(w.acts_bytes);
+  w.order_ws_off = w.order_off + align256(size_t(nvert) * sizeof(int32_t));
+  w.total = w.order_ws_off + align256(relight_order_workspace_bytes(nvert));
   return w;
 }
 
@@ -572,6 +574,12 @@ int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M
       return st;
   }
   T.val = values;
+  // heavy-first processing order of the vertices from their cluster rows
+  int32_t* order = reinterpret_cast<int32_t*>(base + w.order_off);
+  if ((st = launch_relight_order(M->support, cluster, M->nclusters, RRT_MLP_OUT, nvert, L->n,
+                                 order, base + w.order_ws_off, s)))
+    return st;
+  T.order = nvert > 0 ? order : nullptr;
   st = rrt_relight_prepare(L, flags, ws, w.relight_total, stream);
   if (st) return st;
   return rrt_relight_prepared(L, R, &T, radiance, flags, ws, w.relight_total, stream);
