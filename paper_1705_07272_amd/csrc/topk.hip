@@ -171,7 +171,6 @@ constexpr int kLowBits = 31 - kBinBits;  // key bits below the bin
 constexpr int kMaxChunks = 64;
 constexpr int kMinChunk = 4096;
 constexpr int kChunkThreads = 256;
-constexpr int kRowThreads = 1024;
 
 // Per-row parameters in the workspace.
 enum { P_BIN, P_NEED, P_CAND, P_THR, P_CUT, P_COUNT };
