@@ -26,12 +26,23 @@ PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.32 T non-packed 32-bit lane-o
 PEAK_HBM_GBS = 8000.0
 # Algorithmic operations per rotated texel: the gfx950 instructions the
 # exact source map, the gather and the texel's share of the 2x2 levels need
-# (one per VALU instruction or memory access); derivation in the design doc.
-OPS_PER_TEXEL = 27
-# The same count for the chain-rule rotation of the finest level: the exact
-# map, gather and chain rule once per 2x2 destination block, spread over its
-# four texels, plus the share of the levels above the finest one.
-CHAIN_OPS_PER_TEXEL = 21
+# (one per VALU instruction or memory access): the direction from its
+# neighbour's (3 binary32 adds, exact), face, in-face coordinates and major
+# component (4 cube-map instructions), the reciprocal (1), the two
+# coordinates (2 fmas), the face as an integer (1), the exactness test (two
+# masks, their minimum, a compare: 4), the row-major flat index from the
+# significand bits (2 shifts, 2 shift-adds), the gather (1) and the share of
+# the 2x2 levels (4: twelve adds per four texels per level, x 4/3 over the
+# levels).  The strip layout of the source map costs 2 more instructions per
+# texel, counted as overhead.
+OPS_PER_TEXEL = 24
+# The same count for the chain-rule rotation of the finest level: per 2x2
+# destination block the map at n/2 without the levels (19), its 16-byte
+# gather (1), the source face's components (9), reciprocal and square (2),
+# four Jacobian entries (16), two mixed second derivatives (14), the chain
+# rule (9) and the level-1 outputs with their stores (8), spread over the
+# block's four texels (19.5), plus the share of the levels above level 1.
+CHAIN_OPS_PER_TEXEL = 20.5
 # The triple product adds the read of the BRDF factor and the product.
 TRIPLE_EXTRA_OPS = 2
 # Longitude-latitude rule per texel: the centre's sines and cosines (4

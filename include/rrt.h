@@ -40,8 +40,10 @@
  *    The flat coefficient index is face*n*n + row*n + col (int32).
  *  - A rotation is a row-major 3x3 float32 matrix R mapping local directions
  *    to the lighting's frame; the rotated lighting is g(w) = L(R w), sampled
- *    at texel centres with the nearest source texel.  R is quantised to
- *    R_q = rint(R * 2^20) and the source texel is found in exact integer
+ *    at texel centres with the nearest source texel.  For an n x n map R
+ *    is quantised to R_q = rint(R * 2^k), k = 22 - log2(n) (entries of R
+ *    in [-1, 1]; for other matrices the source texels are unspecified but
+ *    always inside the map), and the source texel is found in exact integer
  *    arithmetic (major axis, ties to the lower axis; column
  *    j' = min(n-1, floor(n (sc + |d_a|) / (2 |d_a|))), row likewise), so
  *    results do not depend on floating-point evaluation order.
@@ -186,8 +188,8 @@ typedef struct {
                             and R_v is used as is) */
   const float* vert_rot; /* [V][9] vertex frames (local -> object) */
 } rrt_rotations;
-/* R_fv = (R_q(frame f) R_q(vertex v) + 2^19) >> 20, entry-wise in exact
-   integer arithmetic (flooring shift). */
+/* R_fv = (R_q(frame f) R_q(vertex v) + 2^(k-1)) >> k, k = 22 - log2(n),
+   entry-wise in exact integer arithmetic (flooring shift). */
 
 /* Workspace: the reconstructed source map (6 n^2 values, float32 or
    binary16) plus a 6 n^2 float32 staging buffer (after prepare with

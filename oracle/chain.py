@@ -41,7 +41,7 @@ import numpy as np
 
 from .haar import haar_forward
 from .relight import frame_vertex_rotation, reconstruct_lighting
-from .sphere import SCALE_BITS, source_index
+from .sphere import scale_bits, source_index
 
 # Destination face axes: direction = U eU + V eV + n eN (faces +X..-Z).
 FACE_AXES = np.array([
@@ -79,7 +79,7 @@ def chain_rotate(P, Rq):
     P = np.asarray(P, dtype=np.float64)
     n = P.shape[-1]
     h = n // 2
-    R = np.asarray(Rq, dtype=np.float64) / float(1 << SCALE_BITS)
+    R = np.asarray(Rq, dtype=np.float64) / float(1 << scale_bits(n))
     src = source_index(Rq, h)                                # [6, h, h] flat at n/2
     Bf = source_blocks(P).reshape(-1, 4)[src]                # [6, h, h, 4]
     sface = src // (h * h)
@@ -128,6 +128,6 @@ def relight_chain(light_idx, light_val, n, vert_rot, frame_rot, t_idx, t_val,
         else:
             T[np.asarray(t_idx[v], np.int64)] = vals
         for b, f in enumerate(frames):
-            Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f)
+            Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f, n)
             out[b, a] = np.dot(T, haar_forward(chain_rotate(P, Rq)).ravel())
     return out

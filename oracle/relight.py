@@ -52,18 +52,18 @@ def reconstruct_lighting(idx, val, n):
     return haar_inverse(c.reshape(6, n, n))
 
 
-def frame_vertex_rotation(vert_rot, frame_rot, v, f):
-    """Quantised R_fv: the vertex frame alone when there is no frame rotation,
-    otherwise the fixed-point composition R_obj(f) * F_v."""
-    Fv = quantise_rotation(np.asarray(vert_rot)[v])
+def frame_vertex_rotation(vert_rot, frame_rot, v, f, n):
+    """Quantised R_fv for an n x n map: the vertex frame alone when there is
+    no frame rotation, otherwise the fixed-point composition R_obj(f) * F_v."""
+    Fv = quantise_rotation(np.asarray(vert_rot)[v], n)
     if frame_rot is None:
         return Fv
-    return compose_rotations(quantise_rotation(np.asarray(frame_rot)[f]), Fv)
+    return compose_rotations(quantise_rotation(np.asarray(frame_rot)[f], n), Fv, n)
 
 
 def phase_shift(coef, R):
     """Dense Haar-domain rotation W S(R) W^T coef of one cube map [6, n, n]."""
-    Rq = quantise_rotation(R)
+    Rq = quantise_rotation(R, np.asarray(coef).shape[-1])
     return haar_forward(rotate_pixels(haar_inverse(coef), Rq))
 
 
@@ -94,7 +94,7 @@ def relight(light_idx, light_val, n, vert_rot, frame_rot, t_idx, t_val,
         else:
             T[np.asarray(t_idx[v], np.int64)] = vals
         for b, f in enumerate(frames):
-            Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f)
+            Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f, n)
             ghat = haar_forward(rotate_pixels(P, Rq)).ravel()
             out[b, a] = np.dot(T, ghat)
             scale[b, a] = np.dot(np.abs(T), np.abs(ghat))

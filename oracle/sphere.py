@@ -11,10 +11,14 @@ the six-face cube map and the source of each texel is the texel whose pyramid
 contains R w (nearest texel at texel centres).
 
 To make the result unique (independent of floating-point evaluation order),
-the geometry is exact: R is quantised to integers R_q = rint(R * 2^20), texel
-centres are the integer vectors below, d = R_q * dir is an exact int64
-product, and the source texel follows from integer comparisons and floor
-divisions.
+the geometry is exact: R is quantised to integers R_q = rint(R * 2^k) with
+k = 22 - log2(n) for an n x n map, texel centres are the integer vectors
+below, d = R_q * dir is an exact int64 product, and the source texel follows
+from integer comparisons and floor divisions.  With this k every component of
+d, and every partial sum of its three terms, is an integer of magnitude below
+3 n 2^k = 3 * 2^22 < 2^24 (|R_q| entries <= 2^k, |U|, |V| < n), so the
+directions are also exact binary32 numbers; the rotation itself is resolved
+to 2^-k (2^-15 at n = 128, far below the texel size 2/n).
 
 Face table (faces 0..5 = +X, -X, +Y, -Y, +Z, -Z; texel (i, j) of an n x n
 face has U = 2j+1-n, V = 2i+1-n, the face plane at distance n):
@@ -28,22 +32,27 @@ from tc.
 """
 import numpy as np
 
-SCALE_BITS = 20
+def scale_bits(n):
+    """k = 22 - log2(n): the fixed-point scale of rotations for an n x n map."""
+    n = int(n)
+    assert n >= 1 and n & (n - 1) == 0, n
+    return 22 - (n.bit_length() - 1)
 
 
-def quantise_rotation(R):
-    """R_q = rint(R * 2^20) (round half to even) as int64; R is float32/64
-    of shape [..., 3, 3] (row-major, local -> global)."""
-    return np.rint(np.asarray(R, dtype=np.float64) * float(1 << SCALE_BITS)).astype(np.int64)
+def quantise_rotation(R, n):
+    """R_q = rint(R * 2^k), k = scale_bits(n) (round half to even) as int64;
+    R is float32/64 of shape [..., 3, 3] (row-major, local -> global)."""
+    return np.rint(np.asarray(R, dtype=np.float64) * float(1 << scale_bits(n))).astype(np.int64)
 
 
-def compose_rotations(Ra_q, Rb_q):
-    """Fixed-point product (Ra_q Rb_q + 2^19) >> 20, entry-wise, exact int64
-    with a flooring shift.  Ra is the global object rotation of a frame, Rb a
-    vertex's local frame; the result maps local directions to the lighting's
-    frame."""
+def compose_rotations(Ra_q, Rb_q, n):
+    """Fixed-point product (Ra_q Rb_q + 2^(k-1)) >> k, k = scale_bits(n),
+    entry-wise, exact int64 with a flooring shift.  Ra is the global object
+    rotation of a frame, Rb a vertex's local frame; the result maps local
+    directions to the lighting's frame."""
+    k = scale_bits(n)
     p = np.matmul(np.asarray(Ra_q, np.int64), np.asarray(Rb_q, np.int64))
-    return (p + (1 << (SCALE_BITS - 1))) >> SCALE_BITS
+    return (p + (1 << (k - 1))) >> k
 
 
 def texel_centres(n):

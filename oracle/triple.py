@@ -203,7 +203,7 @@ def relight_triple(light_idx, light_val, n, vert_rot, frame_rot, v_idx, v_val, b
         ci = np.asarray(v_idx[v], np.int64)
         cv = np.asarray(v_val[v], np.float64)
         for bi, f in enumerate(frames):
-            Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f)
+            Rq = frame_vertex_rotation(vert_rot, frame_rot, v, f, n)
             A = rotate_pixels(P, Rq)
             out[bi, ai] = triple_sum(haar_forward(A).ravel(), bcoef[m], ci, cv, n, tables)
             if return_scale:

@@ -238,8 +238,8 @@ int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_
   void* src = base + w.src_off;
   st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, 6, dense, s);
   if (st) return st;
-  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, 6, s)
-           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 6, s);
+  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, 6, s, true)
+           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 6, s, true);
   if (st || !(flags & RRT_CHAIN_RULE)) return st;
   // the staging buffer is free now: it takes the 2x2 block coefficients
   return launch_source_blocks(src, f16, L->n, dense, s);

@@ -9,35 +9,40 @@
 
 namespace rrt {
 
-constexpr int kScaleBits = 20;  // R_q = rint(R * 2^20)
+// Rotations of an n x n map are quantised to R_q = rint(R 2^k), k = 22 -
+// log2(n).  A texel direction R_q (U eU + V eV + n eN) with |U|, |V| < n, and
+// every partial sum of its terms, is then an integer of magnitude below
+// 3 n 2^k = 3 2^22 < 2^24: exact in binary32, so directions are formed with
+// binary32 adds and fmas and fed to the cube-map instructions unrounded.
+__device__ __forceinline__ int scale_bits(int logn) { return 22 - logn; }
 
 // Quantised rotation, row-major int32.
 struct IRot {
   int m[9];
 };
 
-__device__ __forceinline__ int quantise_entry(float r) {
-  return int(rintf(r * float(1 << kScaleBits)));
+__device__ __forceinline__ int quantise_entry(float r, int k) {
+  return int(rintf(ldexpf(r, k)));
 }
 
-// R_fv = (R_q(frame) R_q(vertex) + 2^19) >> 20 (flooring shift), or R_q(vertex).
+// R_fv = (R_q(frame) R_q(vertex) + 2^(k-1)) >> k (flooring shift), or R_q(vertex).
 __device__ __forceinline__ IRot frame_vertex_rotation(const float* __restrict__ vrot,
-                                                      const float* __restrict__ frot) {
+                                                      const float* __restrict__ frot, int k) {
   IRot v, out;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) v.m[k] = quantise_entry(vrot[k]);
+  for (int e = 0; e < 9; ++e) v.m[e] = quantise_entry(vrot[e], k);
   if (frot == nullptr) return v;
   int f[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) f[k] = quantise_entry(frot[k]);
+  for (int e = 0; e < 9; ++e) f[e] = quantise_entry(frot[e], k);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      int64_t acc = int64_t(1) << (kScaleBits - 1);
+      int64_t acc = int64_t(1) << (k - 1);
 #pragma unroll
       for (int m = 0; m < 3; ++m) acc += int64_t(f[3 * i + m]) * int64_t(v.m[3 * m + j]);
-      out.m[3 * i + j] = int(acc >> kScaleBits);
+      out.m[3 * i + j] = int(acc >> k);
     }
   return out;
 }
@@ -46,9 +51,10 @@ __device__ __forceinline__ IRot frame_vertex_rotation(const float* __restrict__ 
 // faces +X,-X,+Y,-Y,+Z,-Z:
 //   +X ( n,-V,-U)  -X (-n,-V, U)  +Y ( U, n, V)
 //   -Y ( U,-n,-V)  +Z ( U,-V, n)  -Z (-U,-V,-n).
-// Each axis is a signed unit vector: encoded as axis index and sign.
+// Each axis is a signed unit vector: encoded as axis index and sign.  The
+// rotated axes hold the integer entries of R_q (|entry| <= 2^k), exactly.
 struct FaceAxes {
-  int3 mU, mV, mN;  // R * eU, R * eV, R * eN
+  float3 mU, mV, mN;  // R * eU, R * eV, R * eN
 };
 
 __device__ __forceinline__ int pick3(int a, int b, int c, int axis) {
@@ -56,10 +62,10 @@ __device__ __forceinline__ int pick3(int a, int b, int c, int axis) {
 }
 
 // sign * (column `axis` of R), without dynamic register indexing.
-__device__ __forceinline__ int3 signed_column(const IRot& R, int axis, int sign) {
-  return make_int3(sign * pick3(R.m[0], R.m[1], R.m[2], axis),
-                   sign * pick3(R.m[3], R.m[4], R.m[5], axis),
-                   sign * pick3(R.m[6], R.m[7], R.m[8], axis));
+__device__ __forceinline__ float3 signed_column(const IRot& R, int axis, int sign) {
+  return make_float3(float(sign * pick3(R.m[0], R.m[1], R.m[2], axis)),
+                     float(sign * pick3(R.m[3], R.m[4], R.m[5], axis)),
+                     float(sign * pick3(R.m[6], R.m[7], R.m[8], axis)));
 }
 
 __device__ __forceinline__ FaceAxes face_axes(const IRot& R, int face) {
@@ -77,11 +83,16 @@ __device__ __forceinline__ FaceAxes face_axes(const IRot& R, int face) {
   return a;
 }
 
-// Modular int32 arithmetic: the true direction components fit in int32 for
-// n <= 1024 (|R_q| <= 2^20, |dir| <= n sqrt(3)), so wrapped partial sums still
-// give the exact final value.
-__device__ __forceinline__ int wrap_mad(int a, int b, int c) {
-  return int(unsigned(a) * unsigned(b) + unsigned(c));
+// Direction a U + b V + c (three components), exact for the integer
+// operands described at scale_bits.
+__device__ __forceinline__ float3 dir_mad(float3 u, float a, float3 v, float b, float3 c) {
+  return make_float3(__builtin_fmaf(u.x, a, __builtin_fmaf(v.x, b, c.x)),
+                     __builtin_fmaf(u.y, a, __builtin_fmaf(v.y, b, c.y)),
+                     __builtin_fmaf(u.z, a, __builtin_fmaf(v.z, b, c.z)));
+}
+__device__ __forceinline__ float3 dir_add(float3 u, float a, float3 c) {
+  return make_float3(__builtin_fmaf(u.x, a, c.x), __builtin_fmaf(u.y, a, c.y),
+                     __builtin_fmaf(u.z, a, c.z));
 }
 
 // floor(s * 2^logh / D) exactly, given q0 within one of it (|s| <= D, D >= 1):
@@ -134,53 +145,107 @@ __device__ __forceinline__ int source_texel_exact(int x, int y, int z, int logn)
 // The same map, with a binary32 fast path on the cube-map instructions
 // (v_cubeid / v_cubesc / v_cubetc / v_cubema: face, in-face coordinates and
 // twice the major component, in the face convention above, ties resolved
-// towards z then y), returned scaled by 2^ES (a byte offset for elements of
-// 2^ES bytes).
+// towards z then y), for a direction given as exact binary32 integers.
 //
-// The components are converted to binary32 (relative error 2^-24 each; sc
-// and D are copies of them, |ma| = 2 D exactly) and q = h sc / D + h + eps
-// is estimated as fma(sc, n rcp(|ma|), h + eps): sc / D is off by at most
-// 2^-23 relative, v_rcp_f32 by one ulp (2^-23), so the product is within
-// h 2^-22 of h sc / D, and the fma rounds once (at most h 2^-23): the error
-// is below 1.5 h 2^-22 < eps = h 2^-20 (quotient_margin).  If frac(q) >= 2 eps
-// for both coordinates, the exact quotient lies strictly between the same
-// two integers as q - eps, so trunc(q) is the exact floor (and lies in
-// [0, n - 1]); otherwise the exact form replaces the result.
+// The fast path works on x = q / n + 1 + e, q = h sc / D + h the exact texel
+// coordinate and e = 2^-22, so that x lies in (1, 2) and the bits of its
+// significand are q's: the top log2(n) bits are floor(q + n e), the rest its
+// fraction.  sc and |ma| = 2 D are exact, v_rcp_f32 is within one ulp
+// (2^-23 relative), so sc / |ma| (at most 1/2) is within 2^-24 of the exact
+// ratio, and the fma that adds 3/2 + e rounds once (at most 2^-24): x is
+// within 2^-23 = e / 2 of its exact value.  If the fraction bits of both
+// coordinates are at least 4 (the fraction of n (x - 1) is at least 2 n e),
+// the exact q lies strictly between the same two integers, so the top bits
+// are the exact floor (in [0, n - 1]); otherwise the exact form replaces the
+// result.  An estimate at or above 2 has fraction bits below 4 (x < 2 + 3/2 e)
+// and also takes the exact form.
 //
-// A face chosen by the binary32 comparison that differs from the exact one
-// (a near tie |d_a| ~ |d_b| or an exact tie broken the other way) is always
-// caught: the exact major component then appears as an in-face coordinate
-// with |a_f| / |b_f| in [1 - 2^-23, 1], so that coordinate's q - eps is
-// within h 2^-23 + 1.5 h 2^-22 = h 2^-21 < eps of 0 or 2h and fails the
-// margin test.  A zero direction gives NaN and also takes the exact form.
-// Every output is in [0, 6 n^2) << ES.
-template <int ES>
-__device__ __forceinline__ unsigned source_texel_scaled(int x, int y, int z, int logn, float eps) {
-  const float fx = float(x), fy = float(y), fz = float(z);
-  const float ma = __builtin_amdgcn_cubema(fx, fy, fz);
-  const float hr = float(1 << logn) * __builtin_amdgcn_rcpf(fabsf(ma));
-  const float off = float(1 << (logn - 1)) + eps;
-  const float qs = __builtin_fmaf(__builtin_amdgcn_cubesc(fx, fy, fz), hr, off);
-  const float qt = __builtin_fmaf(__builtin_amdgcn_cubetc(fx, fy, fz), hr, off);
-  // q > 0, so truncation is the floor; the flat index (face n + i) n + j is
-  // below 6 * 2^20 < 2^24 and so exact in binary32 arithmetic
-  const float js = __builtin_truncf(qs), it = __builtin_truncf(qt);
-  const float es = qs - js, et = qt - it;
-  const float nf = float(1 << logn);
-  const float flat = __builtin_fmaf(__builtin_amdgcn_cubeid(fx, fy, fz), nf * nf,
-                                    __builtin_fmaf(it, nf, js));
-  unsigned at = unsigned(flat) << ES;
-  if (!(fminf(es, et) >= 2.0f * eps)) at = unsigned(source_texel_exact(x, y, z, logn)) << ES;
+// With exact components the binary32 face comparison can differ from the
+// exact one only at an exact tie broken the other way; the exact major
+// component is then an in-face coordinate equal to +-D, whose x is within
+// e / 2 of 1 + e or 2 + e, where the fraction test fails.  A zero direction
+// gives NaN, whose fraction bits are zero for n >= 2: the exact form.
+// 127 (n^2 + n): the offset that the significand bits of x add to a flat
+// index (see source_texel_biased).
+__device__ __forceinline__ unsigned texel_bias(int logn) {
+  return (127u << (2 * logn)) + (127u << logn);
+}
+
+// Strip layout of a source map (n >= 4): global rows R = face n + i are
+// grouped in strips of four, each strip stored column by column, so texel
+// (R, j) sits at ((R >> 2) << (log2 n + 2)) + 4 j + (R & 3) and a 4-row x
+// 8-column patch (32 binary32 values) shares one 128-byte cache line.  A
+// rotated 8 x 8 patch of destination texels then touches about half the
+// lines it touches in row-major order.
+__device__ __forceinline__ unsigned strip_offset(unsigned R, unsigned j, int logn) {
+  return ((R >> 2) << (logn + 2)) + (j << 2) + (R & 3u);
+}
+// 127 n^2: the offset of the strip index built from significand bits.
+__device__ __forceinline__ unsigned strip_bias(int logn) { return 127u << (2 * logn); }
+
+// Fast path of the map (see source_texel_biased for the error analysis):
+// significands of x for both in-face coordinates, the face, and whether the
+// top bits are exact floors.
+struct FastTexel {
+  unsigned bs, bt, face;
+  bool ok;
+};
+__device__ __forceinline__ FastTexel fast_texel(float fx, float fy, float fz, int logn) {
+  const float r = __builtin_amdgcn_rcpf(fabsf(__builtin_amdgcn_cubema(fx, fy, fz)));
+  constexpr float kOff = 1.5f + 0x1p-22f;
+  FastTexel t;
+  t.bs = __float_as_uint(__builtin_fmaf(__builtin_amdgcn_cubesc(fx, fy, fz), r, kOff));
+  t.bt = __float_as_uint(__builtin_fmaf(__builtin_amdgcn_cubetc(fx, fy, fz), r, kOff));
+  t.face = unsigned(__builtin_amdgcn_cubeid(fx, fy, fz));
+  // fraction bits at least 4 in both: some bit of [2, 23 - log2 n) set in each
+  const unsigned fr = ((1u << (23 - logn)) - 1u) & ~3u;
+  t.ok = min(t.bs & fr, t.bt & fr) != 0u;
+  return t;
+}
+
+// Flat source texel plus texel_bias(logn), so that the fast path needs no
+// subtraction; in [texel_bias, texel_bias + 6 n^2).
+__device__ __forceinline__ unsigned source_texel_biased(float fx, float fy, float fz, int logn) {
+  const FastTexel t = fast_texel(fx, fy, fz, logn);
+  // for x in (1, 2), the bits above the fraction are 127 n + column (or row)
+  const int sh = 23 - logn;
+  const unsigned rows = (t.face << logn) + (t.bt >> sh);   // face n + 127 n + i
+  unsigned at = (rows << logn) + (t.bs >> sh);             // flat + 127 n^2 + 127 n
+  if (!t.ok) at = unsigned(source_texel_exact(int(fx), int(fy), int(fz), logn)) + texel_bias(logn);
   return at;
 }
 
-__device__ __forceinline__ int source_texel(int x, int y, int z, int logn, float eps) {
-  return int(source_texel_scaled<0>(x, y, z, logn, eps));
+// Strip offset (strip_offset) of the source texel plus strip_bias(logn), for
+// n >= 4; in [strip_bias, strip_bias + 6 n^2).
+__device__ __forceinline__ unsigned source_texel_strip(float fx, float fy, float fz, int logn) {
+  const FastTexel t = fast_texel(fx, fy, fz, logn);
+  const int sh = 23 - logn;
+  // low part 4 j + (i & 3): column bits from bs, the row's two low bits from
+  // bt's top part 127 n + i (127 n is a multiple of 4 for n >= 4)
+  const unsigned lo = ((t.bt >> sh) & 3u) | ((t.bs >> (sh - 2)) & ~3u);
+  // high part (strip (face + 127) n / 4 + (i >> 2)) << (log2 n + 2): the bits
+  // of ((face + 127) n + i) n above log2 n + 2 (bt shifted to that scale
+  // carries fraction bits below log2 n, which the mask drops)
+  const unsigned R = (t.face << (2 * logn)) + (t.bt >> (sh - logn));
+  const unsigned hi = ~((4u << logn) - 1u);
+  // (R & hi) | (lo & ~hi) in one v_bfi_b32 (the mask is loop-invariant, so the
+  // compiler would otherwise not see its complement and emit two operations)
+  unsigned at;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(at) : "s"(hi), "v"(R), "v"(lo));
+  if (!t.ok) {
+    const unsigned q = unsigned(source_texel_exact(int(fx), int(fy), int(fz), logn));
+    at = strip_offset(q >> logn, q & ((1u << logn) - 1u), logn) + strip_bias(logn);
+  }
+  return at;
 }
 
-// Margin of the binary32 quotient estimate (see source_texel).
-__device__ __forceinline__ float quotient_margin(int logn) {
-  return float(1 << (logn - 1)) * 0x1p-20f;
+template <int ES>
+__device__ __forceinline__ unsigned source_texel_scaled(float fx, float fy, float fz, int logn) {
+  return (source_texel_biased(fx, fy, fz, logn) - texel_bias(logn)) << ES;
+}
+
+__device__ __forceinline__ int source_texel(float3 d, int logn) {
+  return int(source_texel_scaled<0>(d.x, d.y, d.z, logn));
 }
 
 }  // namespace rrt

@@ -139,11 +139,13 @@ __device__ __forceinline__ __half to_out<__half>(float x) {
 }
 
 // grid: count * 6 * G * G; the tile sum comes from coef[face][0] when G == 1,
-// else from stage[face * n * n + ty * rs + tx * cs].
+// else from stage[face * n * n + ty * rs + tx * cs].  With `strips` (n >= 4)
+// the pixels are written in strips of four rows, each strip column by column:
+// row r, column c of a square at ((r >> 2) << (log2 n + 2)) + 4 c + (r & 3).
 template <typename OutT>
 __global__ __launch_bounds__(kThreads) void haar_inv_tiles(const float* coef, const float* stage,
                                                            OutT* pix, int n, int logq, int G,
-                                                           int64_t rs, int64_t cs) {
+                                                           int64_t rs, int64_t cs, bool strips) {
   extern __shared__ float lds[];
   const int Q = 1 << logq;
   const int64_t blk = blockIdx.x;
@@ -173,9 +175,18 @@ __global__ __launch_bounds__(kThreads) void haar_inv_tiles(const float* coef, co
     __syncthreads();
   }
   const int row0 = ty * Q, col0 = tx * Q;
-  for (int e = threadIdx.x; e < Q * Q; e += kThreads) {
-    const int r = e >> logq, c = e & (Q - 1);
-    dst[int64_t(row0 + r) * n + col0 + c] = to_out<OutT>(lds[e]);
+  if (strips) {
+    // consecutive threads write consecutive elements of a strip
+    for (int e = threadIdx.x; e < Q * Q; e += kThreads) {
+      const int st = e >> (logq + 2), c = (e >> 2) & (Q - 1), rl = e & 3;
+      const int r = 4 * st + rl;
+      dst[int64_t((row0 + r) >> 2) * 4 * n + 4 * (col0 + c) + rl] = to_out<OutT>(lds[r * Q + c]);
+    }
+  } else {
+    for (int e = threadIdx.x; e < Q * Q; e += kThreads) {
+      const int r = e >> logq, c = e & (Q - 1);
+      dst[int64_t(row0 + r) * n + col0 + c] = to_out<OutT>(lds[e]);
+    }
   }
 }
 
@@ -194,11 +205,14 @@ int launch_haar_forward(const float* pix, float* coef, int n, int64_t squares, h
   return check_launch("haar_fwd_coarse");
 }
 
-int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s) {
+int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s,
+                        bool strips) {
   if (squares == 0) return RRT_OK;
+  if (n < 4) strips = false;
   const int Q = n < kTile ? n : kTile;
   const int G = n / Q;
-  const int64_t rs = int64_t(Q) * n, cs = Q;       // first texel of each output tile
+  // first texel of each output tile (also in strips: tile rows start strips)
+  const int64_t rs = int64_t(Q) * n, cs = strips ? 4 * Q : Q;
   if (G > 1) {
     hipLaunchKernelGGL(haar_inv_coarse, dim3(unsigned(squares)), dim3(64), 0, s, coef, pix, n,
                        G, rs, cs);
@@ -208,14 +222,15 @@ int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, h
   const int64_t grid = squares * G * G;
   hipLaunchKernelGGL(haar_inv_tiles<float>, dim3(unsigned(grid)), dim3(kThreads),
                      size_t(Q) * Q * sizeof(float), s, coef, (const float*)pix, pix, n, ilog2(Q),
-                     G, rs, cs);
+                     G, rs, cs, strips);
   return check_launch("haar_inv_tiles");
 }
 
 // `coef` is the caller's own dense staging buffer: for n > 128 its Mallat
 // corner is overwritten by the tile sums (spatial order).
 int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
-                            hipStream_t s) {
+                            hipStream_t s, bool strips) {
+  if (n < 4) strips = false;
   const int Q = n < kTile ? n : kTile;
   const int G = n / Q;
   const int64_t rs = n, cs = 1;
@@ -227,7 +242,7 @@ int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int 
   }
   hipLaunchKernelGGL(haar_inv_tiles<__half>, dim3(unsigned(squares * G * G)), dim3(kThreads),
                      size_t(Q) * Q * sizeof(float), s, coef, (const float*)staging, pix, n,
-                     ilog2(Q), G, rs, cs);
+                     ilog2(Q), G, rs, cs, strips);
   return check_launch("haar_inv_tiles_f16");
 }
 

@@ -51,29 +51,42 @@ constexpr int kGroupBytes = 4096;
 // most 1,024 blocks: kGroupBytes / 8, or one face of 32 x 32 blocks)
 constexpr int kBlockMaskBytes = 128;
 
-// Gathers from the source map go through a raw buffer resource: 32-bit
-// offsets (no 64-bit address arithmetic per texel) and hardware range
-// checking (reads past the map return 0).
-constexpr int kBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+// Gathers from the source map go through a structured buffer resource whose
+// stride is the element size: the element index is the whole per-texel
+// address computation (no 64-bit arithmetic, no byte scaling), and the
+// hardware checks the index against the element count (reads past the map
+// return 0).  The structured loads are the LLVM intrinsics themselves.
+constexpr int kBufferWord3 = 0x00020000;  // gfx9 buffer: 32-bit data format
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+extern "C" __device__ float rrt_struct_load_f32(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
+                                                int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.f32");
+extern "C" __device__ short rrt_struct_load_i16(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
+                                                int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.i16");
 
+// Resource over `count` elements at p, addressed with indices offset by
+// `bias` (element i of the map is index bias + i; the cube-map gather hands
+// texel_bias-offset indices straight to the load, which by construction are
+// never below the bias).
 template <typename SrcT>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const SrcT* p, int count) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<SrcT*>(p), short(0),
-                                           count * int(sizeof(SrcT)), kBufferWord3);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const SrcT* p, int count,
+                                                                  unsigned bias) {
+  const uintptr_t base = reinterpret_cast<uintptr_t>(p) - uintptr_t(bias) * sizeof(SrcT);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), short(sizeof(SrcT)),
+                                           count + int(bias), kBufferWord3);
 }
 
-// Element of the source map at byte offset `at`.
+// Element `at` of the source map.
 template <typename SrcT>
 __device__ __forceinline__ float load_src(__amdgpu_buffer_rsrc_t r, unsigned at);
 template <>
 __device__ __forceinline__ float load_src<float>(__amdgpu_buffer_rsrc_t r, unsigned at) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, int(at), 0, 0));
+  return rrt_struct_load_f32(r, int(at), 0, 0, 0);
 }
 template <>
 __device__ __forceinline__ float load_src<__half>(__amdgpu_buffer_rsrc_t r, unsigned at) {
-  const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, int(at), 0, 0);
-  return __half2float(__ushort_as_half(b));
+  return __half2float(__short_as_half(rrt_struct_load_i16(r, int(at), 0, 0, 0)));
 }
 
 // OCP E4M3FN: s eeee mmm, bias 7, subnormals, 0x7f/0xff NaN, no infinities.
@@ -422,9 +435,11 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   const int G = n >> LOGQ;  // blocks per face side
   const int G2 = G * G;
   const int FG = p.group_faces;
-  const __amdgpu_buffer_rsrc_t src =
-      source_resource(static_cast<const SrcT*>(p.src), NF * (n << logn));
-  const float eps = quotient_margin(logn);
+  // the cube map's source map is in strips of four rows for n >= 4 (Q >= 4)
+  constexpr bool STRIPS = Q >= 4 && !LL;
+  const __amdgpu_buffer_rsrc_t src = source_resource(
+      static_cast<const SrcT*>(p.src), NF * (n << logn),
+      LL ? 0u : (STRIPS ? strip_bias(logn) : texel_bias(logn)));
   const bool comp = p.comp != 0;
 
   float* img = reinterpret_cast<float*>(dyn_lds);  // the block image
@@ -495,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   for (int f = 0; f < p.nframes; ++f) {
     IRot R = {};
     if constexpr (!LL) {
-      R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr);
+      R = frame_vertex_rotation(p.vrot + v * 9, p.frot ? p.frot + f * 9 : nullptr, scale_bits(logn));
 #pragma unroll
       for (int k = 0; k < 9; ++k) R.m[k] = __builtin_amdgcn_readfirstlane(R.m[k]);
     }
@@ -540,16 +555,14 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
         const FaceAxes ax = face_axes(R, face);
         // this lane's direction at texel (ty, tx) of block (0, 0); a block
         // (by, bx) adds the uniform 2 Q (bx R e_U + by R e_V)
-        const int U0 = 2 * tx + 1 - n, V0 = 2 * ty + 1 - n;
-        const int lx = wrap_mad(ax.mU.x, U0, wrap_mad(ax.mV.x, V0, wrap_mad(ax.mN.x, n, 0)));
-        const int ly = wrap_mad(ax.mU.y, U0, wrap_mad(ax.mV.y, V0, wrap_mad(ax.mN.y, n, 0)));
-        const int lz = wrap_mad(ax.mU.z, U0, wrap_mad(ax.mV.z, V0, wrap_mad(ax.mN.z, n, 0)));
+        // (exact binary32 integers throughout, see scale_bits)
+        const float3 zero3 = make_float3(0.0f, 0.0f, 0.0f);
+        const float3 l0 = dir_mad(ax.mU, float(2 * tx + 1 - n), ax.mV, float(2 * ty + 1 - n),
+                                  dir_add(ax.mN, float(n), zero3));
         // chain rule: the lane's destination block (ty, tx) at half resolution
         const int hn = n >> 1;
-        const int Uh = 2 * tx + 1 - hn, Vh = 2 * ty + 1 - hn;
-        const int hx = wrap_mad(ax.mU.x, Uh, wrap_mad(ax.mV.x, Vh, wrap_mad(ax.mN.x, hn, 0)));
-        const int hy = wrap_mad(ax.mU.y, Uh, wrap_mad(ax.mV.y, Vh, wrap_mad(ax.mN.y, hn, 0)));
-        const int hz = wrap_mad(ax.mU.z, Uh, wrap_mad(ax.mV.z, Vh, wrap_mad(ax.mN.z, hn, 0)));
+        const float3 h0 = dir_mad(ax.mU, float(2 * tx + 1 - hn), ax.mV, float(2 * ty + 1 - hn),
+                                  dir_add(ax.mN, float(hn), zero3));
         for (int by = 0; by < G; ++by) {
           for (int bx = 0; bx < G; ++bx, ++gi) {
             // entries past the list may fall in any block: then every block is full
@@ -569,8 +582,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
                     const int i = by * Q + TS * a + ty;
                     const int jc = (face * n + bx * Q + TS * b + tx + llsc) & (2 * n - 1);
                     val[a][b] = load_src<SrcT>(
-                        src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa)
-                                 << (sizeof(SrcT) == 4 ? 2 : 1));
+                        src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa));
                   }
                 if (full) {
 #pragma unroll
@@ -587,38 +599,29 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
               // the chain rule; level-1 coefficients go straight to the image.
               const __amdgpu_buffer_rsrc_t blk = __builtin_amdgcn_make_buffer_rsrc(
                   const_cast<float4*>(p.blocks), short(0), 6 * hn * hn * 16, kBufferWord3);
-              const float eps_h = quotient_margin(logn - 1);
-              const int rx = wrap_mad(ax.mU.x, 2 * (Q / 2) * bx, wrap_mad(ax.mV.x, 2 * (Q / 2) * by, hx));
-              const int ry = wrap_mad(ax.mU.y, 2 * (Q / 2) * bx, wrap_mad(ax.mV.y, 2 * (Q / 2) * by, hy));
-              const int rz = wrap_mad(ax.mU.z, 2 * (Q / 2) * bx, wrap_mad(ax.mV.z, 2 * (Q / 2) * by, hz));
+              const float3 rb = dir_mad(ax.mU, float(2 * (Q / 2) * bx), ax.mV, float(2 * (Q / 2) * by), h0);
               float4 cf[2][2];
               int sf[2][2];
 #pragma unroll
               for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                  const int dx = wrap_mad(ax.mU.x, 16 * b, wrap_mad(ax.mV.x, 16 * a, rx));
-                  const int dy = wrap_mad(ax.mU.y, 16 * b, wrap_mad(ax.mV.y, 16 * a, ry));
-                  const int dz = wrap_mad(ax.mU.z, 16 * b, wrap_mad(ax.mV.z, 16 * a, rz));
-                  const unsigned at = source_texel_scaled<4>(dx, dy, dz, logn - 1, eps_h);
+                  const float3 d = dir_mad(ax.mU, float(16 * b), ax.mV, float(16 * a), rb);
+                  const unsigned at = source_texel_scaled<4>(d.x, d.y, d.z, logn - 1);
                   sf[a][b] = int(at >> (2 * (logn - 1) + 4));
                   const u32x4_t raw = __builtin_amdgcn_raw_buffer_load_b128(blk, int(at), 0, 0);
                   cf[a][b] = make_float4(__uint_as_float(raw.x), __uint_as_float(raw.y),
                                          __uint_as_float(raw.z), __uint_as_float(raw.w));
                 }
-              const float3 ex = make_float3(2.0f * float(ax.mU.x), 2.0f * float(ax.mU.y),
-                                            2.0f * float(ax.mU.z));
-              const float3 ey = make_float3(2.0f * float(ax.mV.x), 2.0f * float(ax.mV.y),
-                                            2.0f * float(ax.mV.z));
+              const float3 ex = make_float3(2.0f * ax.mU.x, 2.0f * ax.mU.y, 2.0f * ax.mU.z);
+              const float3 ey = make_float3(2.0f * ax.mV.x, 2.0f * ax.mV.y, 2.0f * ax.mV.z);
 #pragma unroll
               for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                   // the block centre at full resolution: twice the half-resolution direction
-                  const int dx = wrap_mad(ax.mU.x, 16 * b, wrap_mad(ax.mV.x, 16 * a, rx));
-                  const int dy = wrap_mad(ax.mU.y, 16 * b, wrap_mad(ax.mV.y, 16 * a, ry));
-                  const int dz = wrap_mad(ax.mU.z, 16 * b, wrap_mad(ax.mV.z, 16 * a, rz));
-                  const float3 dc = make_float3(2.0f * float(dx), 2.0f * float(dy), 2.0f * float(dz));
+                  const float3 d = dir_mad(ax.mU, float(16 * b), ax.mV, float(16 * a), rb);
+                  const float3 dc = make_float3(2.0f * d.x, 2.0f * d.y, 2.0f * d.z);
                   const float4 o = chain_block(cf[a][b], sf[a][b], dc, ex, ey, float(hn));
                   const int r0 = 2 * (8 * a + ty), c0 = 2 * (8 * b + tx);
                   img[r0 * STRIDE + c0] = o.x;
@@ -631,26 +634,21 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             // covers a compact patch, which the L1 serves with few cache lines):
             // lane (ty, tx) takes texel (TS a + ty, TS b + tx) of every patch
             // (a, b) and stores it raw into the block image.
-              int rx = wrap_mad(ax.mU.x, 2 * Q * bx, wrap_mad(ax.mV.x, 2 * Q * by, lx));
-              int ry = wrap_mad(ax.mU.y, 2 * Q * bx, wrap_mad(ax.mV.y, 2 * Q * by, ly));
-              int rz = wrap_mad(ax.mU.z, 2 * Q * bx, wrap_mad(ax.mV.z, 2 * Q * by, lz));
+              float3 rw = dir_mad(ax.mU, float(2 * Q * bx), ax.mV, float(2 * Q * by), l0);
               // all T^2 loads are issued before the first store, so that they
               // are in flight together
               float val[T][T];
 #pragma unroll
               for (int a = 0; a < T; ++a) {
-                int dx = rx, dy = ry, dz = rz;
+                float3 d = rw;
 #pragma unroll
                 for (int b = 0; b < T; ++b) {
                   val[a][b] = load_src<SrcT>(
-                      src, source_texel_scaled<sizeof(SrcT) == 4 ? 2 : 1>(dx, dy, dz, logn, eps));
-                  dx = wrap_mad(ax.mU.x, 2 * TS, dx);
-                  dy = wrap_mad(ax.mU.y, 2 * TS, dy);
-                  dz = wrap_mad(ax.mU.z, 2 * TS, dz);
+                      src, STRIPS ? source_texel_strip(d.x, d.y, d.z, logn)
+                             : source_texel_biased(d.x, d.y, d.z, logn));
+                  d = dir_add(ax.mU, float(2 * TS), d);
                 }
-                rx = wrap_mad(ax.mV.x, 2 * TS, rx);
-                ry = wrap_mad(ax.mV.y, 2 * TS, ry);
-                rz = wrap_mad(ax.mV.z, 2 * TS, rz);
+                rw = dir_add(ax.mV, float(2 * TS), rw);
               }
               if (full) {
 #pragma unroll
@@ -825,9 +823,11 @@ __global__ void source_blocks_kernel(const SrcT* __restrict__ src, int logn,
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= 6 << (2 * hl)) return;
   const int f = q >> (2 * hl), bi = (q >> hl) & ((1 << hl) - 1), bj = q & ((1 << hl) - 1);
-  const int at = (f << (2 * logn)) + ((2 * bi) << logn) + 2 * bj;
-  const float a = float(src[at]), b = float(src[at + 1]);
-  const float c = float(src[at + (1 << logn)]), d = float(src[at + (1 << logn) + 1]);
+  // the source map is in strips of four rows (n >= 32 here): the block's
+  // two rows share a strip, its columns are four elements apart
+  const unsigned at = strip_offset(unsigned((f << logn) + 2 * bi), unsigned(2 * bj), logn);
+  const float a = float(src[at]), b = float(src[at + 4]);
+  const float c = float(src[at + 1]), d = float(src[at + 5]);
   blocks[q] = make_float4(0.5f * ((a + b) + (c + d)), 0.5f * ((a - b) + (c - d)),
                           0.5f * ((a + b) - (c + d)), 0.5f * ((a - b) - (c - d)));
 }
@@ -954,17 +954,16 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (q >= 6 * per_face) return;
-  const IRot R = frame_vertex_rotation(rot + int64_t(r) * 9, nullptr);
+  const IRot R = frame_vertex_rotation(rot + int64_t(r) * 9, nullptr, scale_bits(logn));
   const int face = q >> (2 * logn);
   const int i = (q >> logn) & (n - 1), j = q & (n - 1);
   const FaceAxes ax = face_axes(R, face);
   const int U = 2 * j + 1 - n, V = 2 * i + 1 - n;
-  const int dx = wrap_mad(ax.mU.x, U, wrap_mad(ax.mV.x, V, wrap_mad(ax.mN.x, n, 0)));
-  const int dy = wrap_mad(ax.mU.y, U, wrap_mad(ax.mV.y, V, wrap_mad(ax.mN.y, n, 0)));
-  const int dz = wrap_mad(ax.mU.z, U, wrap_mad(ax.mV.z, V, wrap_mad(ax.mN.z, n, 0)));
+  const float3 d = dir_mad(ax.mU, float(U), ax.mV, float(V),
+                           dir_add(ax.mN, float(n), make_float3(0.0f, 0.0f, 0.0f)));
   // the map stays in [0, 6 n^2) by construction; the clamp keeps this plain
   // pointer read in bounds whatever the rotation holds
-  const unsigned at = unsigned(source_texel(dx, dy, dz, logn, quotient_margin(logn)));
+  const unsigned at = unsigned(source_texel(d, logn));
   dst[int64_t(r) * 6 * per_face + q] = src[min(at, unsigned(6 * per_face - 1))];
 }
 

@@ -26,10 +26,14 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Haar transform launchers (haar.hip).
 // squares: number of n x n squares (a cube map is 6, a longitude-latitude map 2)
 int launch_haar_forward(const float* pix, float* coef, int n, int64_t squares, hipStream_t s);
-int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s);
+// strips: write the pixels in strips of four rows (the cube-map relight's
+// source-map layout, n >= 4; see strip_offset in geometry.h) instead of
+// row-major order
+int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s,
+                        bool strips = false);
 // Inverse transform writing binary16 pixels (source map of the F16 form).
 int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
-                            hipStream_t s);
+                            hipStream_t s, bool strips = false);
 
 // Selection (topk.hip).
 size_t topk_workspace_bytes(int64_t rows, int64_t len, int k);
@@ -45,7 +49,8 @@ int launch_rotate_pixels(const float* src, const float* rot, int nrot, int n, fl
                          hipStream_t s);
 
 struct RelightLaunch {
-  const void* src;          // [6][n][n] (or [2][n][n] lat-long) float32 or binary16 source map
+  const void* src;          // [6][n][n] float32 or binary16 source map, in strips of four rows
+                            // for n >= 4 (row-major for n < 4 and for the [2][n][n] lat-long map)
   bool src_f16;
   const float* vert_rot;    // [V][9]
   const float* frame_rot;   // [F][9] or nullptr

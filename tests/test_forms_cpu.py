@@ -44,7 +44,7 @@ def test_storage_forms_exact_arithmetic():
     got = {k: np.zeros_like(ref) for k in forms}
     for a in range(len(vids)):
         for b, f in enumerate(frames):
-            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], a, f)
+            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], a, f, 128)
             g = haar_forward(rotate_pixels(P, Rq)).ravel()[case["t_idx"][a]]
             ref[b, a] = tv[a] @ g
             for k, x in forms.items():

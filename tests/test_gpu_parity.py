@@ -186,7 +186,7 @@ def test_phase_shift_index_map_exact(rrt, n):
     out = rrt.haar_phase_shift(dev(coef), dev(R)).cpu().numpy().astype(np.float64)
     for r in range(len(R)):
         got = np.rint(haar_inverse(out[r])).astype(np.int64)
-        want = source_index(quantise_rotation(R[r]), n)
+        want = source_index(quantise_rotation(R[r], n), n)
         assert np.array_equal(got, want), (r, int((got != want).sum()))
 
 
@@ -253,7 +253,7 @@ def test_relight_gather_exact(rrt, n):
         out = rrt.relight(n, dev(light_idx), dev(light), dev(np.tile(R, (V, 1, 1))),
                           dev(rows.reshape(V, 1)), dev(np.ones((V, 1), np.float32)))
         got = out.cpu().numpy()[0]
-        want = haar_forward(rotate_pixels(ids, quantise_rotation(R))).ravel()[rows]
+        want = haar_forward(rotate_pixels(ids, quantise_rotation(R, n))).ravel()[rows]
         err = np.abs(got - want)
         assert err.max() < 0.05, (R, int((err >= 0.05).sum()), float(err.max()))
 
@@ -383,7 +383,7 @@ def chain_reference(case):
         idx = case["t_idx"][v].astype(np.int64)
         tv = case["t_val"][v].astype(np.float64)
         for f in range(F):
-            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], v, f)
+            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], v, f, n)
             g = haar_forward(chain_rotate(P, Rq)).ravel()[idx]
             ref[f, v] = np.dot(tv, g)
             scale[f, v] = np.abs(tv * g).sum()

@@ -53,7 +53,7 @@ def test_block_step_is_the_finest_pyramid_level():
 
 def test_identity_rotation_keeps_the_map():
     P = np.random.default_rng(1).normal(size=(6, 16, 16))
-    np.testing.assert_allclose(chain_rotate(P, quantise_rotation(np.eye(3))), P, atol=1e-12)
+    np.testing.assert_allclose(chain_rotate(P, quantise_rotation(np.eye(3), 16)), P, atol=1e-12)
 
 
 def test_cube_group_gives_the_exact_resampling():
@@ -61,7 +61,7 @@ def test_cube_group_gives_the_exact_resampling():
     mats = _cube_group()
     assert len(mats) == 24
     for M in mats:
-        Rq = quantise_rotation(M)
+        Rq = quantise_rotation(M, 8)
         np.testing.assert_allclose(chain_rotate(P, Rq), rotate_pixels(P, Rq), atol=1e-12)
 
 
@@ -69,9 +69,10 @@ def test_first_order_convergence_on_a_smooth_map():
     from scenes.scene import quaternion_rotations
     a = np.array([0.3, -0.5, 0.8])
     b = np.array([0.2, 0.7, -0.1])
-    Rq = quantise_rotation(quaternion_rotations(np.array([0.9, 0.2, -0.3, 0.25])))
+    R = quaternion_rotations(np.array([0.9, 0.2, -0.3, 0.25]))
     errs = []
     for n in (16, 32, 64):
+        Rq = quantise_rotation(R, n)
         w = texel_centres(n).astype(np.float64)
         w /= np.linalg.norm(w, axis=-1, keepdims=True)
         f = (w @ a) ** 2 + np.sin(3 * (w @ b))
@@ -126,7 +127,7 @@ def test_chain_rule_error_on_benchmark_scene():
     for name, M in (("benchmark lighting", P), ("smooth map", smooth)):
         ps, es = [], []
         for R in random_rotations(7, 3):
-            Rq = quantise_rotation(np.asarray(R, np.float32))
+            Rq = quantise_rotation(np.asarray(R, np.float32), w.n)
             a, b = chain_rotate(M, Rq), rotate_pixels(M, Rq)
             ps.append(_psnr(a, b))
             es.append(np.linalg.norm(a - b) / np.linalg.norm(b))

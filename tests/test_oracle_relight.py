@@ -65,7 +65,7 @@ def test_parseval_pixel_domain_loop():
         T = np.zeros(6 * n * n)
         T[ti[v]] = tv[v]
         t_pix = haar_inverse(T.reshape(6, n, n))
-        src = source_index(quantise_rotation(R[v]), n)
+        src = source_index(quantise_rotation(R[v], n), n)
         acc = 0.0
         for f in range(6):
             for i in range(n):
@@ -98,7 +98,7 @@ def test_delta_light():
     ti, tv = transport_rows(T, 6 * n * n)
     out = relight(li, lv, n, R, None, ti, tv)
     for v in range(3):
-        src = source_index(quantise_rotation(R[v]), n).ravel()
+        src = source_index(quantise_rotation(R[v], n), n).ravel()
         tp = haar_inverse(np.asarray(tv[v], np.float64)[np.argsort(ti[v])].reshape(6, n, n)).ravel()
         expect = 4.0 * tp[src == p].sum()
         assert abs(out[0, v] - expect) < 1e-11

@@ -18,8 +18,8 @@ import numpy as np
 import pytest
 
 from oracle.haar import haar_forward, haar_inverse
-from oracle.sphere import (compose_rotations, locate, quantise_rotation,
-                           rotate_pixels, source_index, texel_centres)
+from oracle.sphere import (compose_rotations, locate, quantise_rotation, rotate_pixels,
+                           scale_bits, source_index, texel_centres)
 from scenes.scene import random_rotations, texel_directions
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -42,7 +42,7 @@ def test_golden_index_map():
     with open(os.path.join(GOLDEN, "index_map_n2.txt")) as fh:
         lines = [l.split() for l in fh if l.strip() and not l.startswith("#")]
     R = np.array([float(t) for t in lines[0][1:]]).reshape(3, 3)
-    src = source_index(quantise_rotation(R), 2)
+    src = source_index(quantise_rotation(R, 2), 2)
     for row in lines[1:]:
         f, i, j, sf, si, sj = map(int, row)
         assert src[f, i, j] == sf * 4 + si * 2 + sj
@@ -84,18 +84,18 @@ def test_face_centres_and_adjacency():
 
 @pytest.mark.parametrize("n", [1, 2, 8, 64])
 def test_identity_rotation_is_identity(n):
-    src = source_index(quantise_rotation(np.eye(3)), n)
+    src = source_index(quantise_rotation(np.eye(3), n), n)
     np.testing.assert_array_equal(src.ravel(), np.arange(6 * n * n))
 
 
 @pytest.mark.parametrize("n", [2, 4, 16])
 def test_cube_group_bijection_and_signed_permutation(n):
     for M in cube_group():
-        src = source_index(quantise_rotation(M), n).ravel()
+        src = source_index(quantise_rotation(M, n), n).ravel()
         assert np.array_equal(np.sort(src), np.arange(6 * n * n))
     if n <= 4:
         for M in cube_group():
-            Rq = quantise_rotation(M)
+            Rq = quantise_rotation(M, n)
             cols = []
             for k in range(6 * n * n):
                 e = np.zeros(6 * n * n)
@@ -115,7 +115,7 @@ def test_quarter_turn_haar_action_n2():
     R = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], float)
     rng = np.random.default_rng(3)
     f = rng.normal(size=(6, 2, 2))
-    g = haar_forward(rotate_pixels(f, quantise_rotation(R)))
+    g = haar_forward(rotate_pixels(f, quantise_rotation(R, 2)))
     F = haar_forward(f)
     S, H, V, D = F[2, 0, 0], F[2, 0, 1], F[2, 1, 0], F[2, 1, 1]
     np.testing.assert_allclose([g[2, 0, 0], g[2, 0, 1], g[2, 1, 0], g[2, 1, 1]], [S, -V, H, -D],
@@ -167,37 +167,50 @@ def test_index_map_brute_force(n):
     rots = list(random_rotations(99, 6)) + _boundary_rotations() + cube_group()[:4]
     c = texel_centres(n)
     for R in rots:
-        Rq = quantise_rotation(R)
+        Rq = quantise_rotation(R, n)
         d = np.einsum("km,fijm->fijk", Rq, c)
         f, i, j = locate(d, n)
         for idx in np.ndindex(6, n, n):
             assert (f[idx], i[idx], j[idx]) == _brute_force_source(d[idx], n, frames), (R, idx)
 
 
-def test_quantise_and_compose():
-    Rq = quantise_rotation(np.eye(3))
-    np.testing.assert_array_equal(Rq, np.eye(3, dtype=np.int64) << 20)
+@pytest.mark.parametrize("n", [1, 2, 128, 1024])
+def test_quantise_and_compose(n):
+    k = scale_bits(n)
+    assert k == 22 - int(np.log2(n))
+    Rq = quantise_rotation(np.eye(3), n)
+    np.testing.assert_array_equal(Rq, np.eye(3, dtype=np.int64) << k)
     G = cube_group()
     for A, B in itertools.product(G[:8], G):
-        np.testing.assert_array_equal(compose_rotations(quantise_rotation(A), quantise_rotation(B)),
-                                      quantise_rotation(A @ B))
+        np.testing.assert_array_equal(
+            compose_rotations(quantise_rotation(A, n), quantise_rotation(B, n), n),
+            quantise_rotation(A @ B, n))
     R = random_rotations(5, 16)
     for r in R:
-        np.testing.assert_array_equal(compose_rotations(quantise_rotation(np.eye(3)), quantise_rotation(r)),
-                                      quantise_rotation(r))
+        np.testing.assert_array_equal(
+            compose_rotations(quantise_rotation(np.eye(3), n), quantise_rotation(r, n), n),
+            quantise_rotation(r, n))
     # half-to-even rounding of an exact tie
-    assert quantise_rotation(np.full((3, 3), 2.5 / (1 << 20)))[0, 0] == 2
+    assert quantise_rotation(np.full((3, 3), 2.5 / (1 << k)), n)[0, 0] == 2
 
 
-def test_int32_headroom():
-    # |R_q dir| < 2^31 for every unit-row rotation up to n = 1024
-    n = 1024
+@pytest.mark.parametrize("n", [1, 2, 128, 1024])
+def test_directions_are_exact_binary32_integers(n):
+    """Every term, partial sum and total of R_q (U eU + V eV + n eN) stays
+    below 2^24 in magnitude, so binary32 holds it exactly: the worst case
+    over random rotations and the bound 3 n 2^k = 3 * 2^22."""
+    k = scale_bits(n)
+    assert 3 * n * (1 << k) == 3 << 22 and (3 << 22) < (1 << 24)
     R = random_rotations(7, 2000).astype(np.float64)
-    Rq = quantise_rotation(R)
-    corner = np.array([n, n - 1, n - 1])
+    Rq = quantise_rotation(R, n)
+    assert np.abs(Rq).max() <= (1 << k)
+    corner = np.array([n, n - 1, n - 1]) if n > 1 else np.array([1, 0, 0])
     worst = np.abs(Rq).astype(np.int64) @ corner
-    assert worst.max() < 2 ** 31
-    assert (1 << 20) * np.sqrt(n * n + 2 * (n - 1) ** 2) * (1 + 3e-6) < 2 ** 31
+    assert worst.max() < (1 << 24)
+    # the texel directions themselves round-trip through binary32
+    m = min(n, 16)
+    d = np.einsum("rkm,fijm->rfijk", Rq[:50], texel_centres(m) * (n // m))
+    assert np.array_equal(d.astype(np.float32).astype(np.int64), d)
 
 
 @pytest.mark.parametrize("n", [4, 16])
@@ -207,10 +220,10 @@ def test_cube_group_equivariance(n):
     rng = np.random.default_rng(11)
     P = rng.normal(size=(6, n, n))
     for C in cube_group():
-        Cq = quantise_rotation(C)
+        Cq = quantise_rotation(C, n)
         Pc = rotate_pixels(P, Cq)                       # f'(w) = f(C w)
         for R in random_rotations(13, 3):
-            Rq = quantise_rotation(R)
+            Rq = quantise_rotation(R, n)
             a = rotate_pixels(Pc, Rq)                   # f'(R w) = f(C R w)
-            b = rotate_pixels(P, compose_rotations(Cq, Rq))
+            b = rotate_pixels(P, compose_rotations(Cq, Rq, n))
             np.testing.assert_array_equal(a, b)
