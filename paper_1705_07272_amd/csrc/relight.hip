@@ -283,6 +283,63 @@ constexpr int kOffBits = 11;
 constexpr int kBlockBits = 13;
 constexpr int kLogbShift = kOffBits + kBlockBits;
 
+// x of lane (this lane ^ K), K < 32: one ds_swizzle in bit mode (and mask
+// 0x1f, xor mask K within each 32-lane half), no address register.
+template <int K>
+__device__ __forceinline__ float lane_xor(float x) {
+  static_assert(K > 0 && K < 32, "swizzle xor masks stay inside 32 lanes");
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), (K << 10) | 0x1f));
+}
+
+// One level above the tiles (tiles of side 2 HT form a block of the next
+// level): the four tiles are lanes l, l ^ HT, l ^ HT TS, l ^ (HT TS + HT);
+// lanes with ((tx | ty) & (2 HT - 1)) == 0 write the level's H, V, D into the
+// image and keep the sum.  The last level (2 HT = TS) has one such lane,
+// lane 0, which reads its partners as scalars.
+template <int HT, int TS, int T, int STRIDE>
+__device__ __forceinline__ void tile_level_above(float& s, float* img, int lane, int tx, int ty,
+                                                 bool owns_tile) {
+  float b, c, d;
+  if constexpr (2 * HT == TS) {
+    const int si = __float_as_int(s);
+    b = __int_as_float(__builtin_amdgcn_readlane(si, HT));
+    c = __int_as_float(__builtin_amdgcn_readlane(si, HT * TS));
+    d = __int_as_float(__builtin_amdgcn_readlane(si, HT * TS + HT));
+  } else {
+    b = lane_xor<HT>(s);
+    c = lane_xor<HT * TS>(s);
+    d = lane_xor<HT * TS + HT>(s);
+  }
+  if (owns_tile && ((tx | ty) & (2 * HT - 1)) == 0) {
+    img[(ty * T) * STRIDE + (tx + HT) * T] = (s - b) + (c - d);
+    img[((ty + HT) * T) * STRIDE + tx * T] = (s + b) - (c + d);
+    img[((ty + HT) * T) * STRIDE + (tx + HT) * T] = (s - b) - (c - d);
+    s = (s + b) + (c + d);
+  }
+  if constexpr (4 * HT <= TS) tile_level_above<2 * HT, TS, T, STRIDE>(s, img, lane, tx, ty, owns_tile);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), the same value in every
+// lane: DPP adds within each 16-lane row (partner in the quad at xor 1 and
+// xor 2, then the mirrored quad of the half row, then the mirrored half row),
+// then the four row sums read back as scalars.
+__device__ __forceinline__ float wave_sum(float x) {
+  x += dpp_mov<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_mov<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_mov<0x141>(x);  // row_half_mirror
+  x += dpp_mov<0x140>(x);  // row_mirror
+  const int xi = __float_as_int(x);
+  return (__int_as_float(__builtin_amdgcn_readlane(xi, 0)) +
+          __int_as_float(__builtin_amdgcn_readlane(xi, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(xi, 32)) +
+          __int_as_float(__builtin_amdgcn_readlane(xi, 48)));
+}
+
 // LDS ordering among the lanes of one wave (no workgroup barrier).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -661,9 +718,8 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
             }
             if (SUM_ONLY && !full) {
               // the block's sum for the levels above it; nothing else reads it
-#pragma unroll
-              for (int o = 1; o < kThreads; o <<= 1) lane_sum += __shfl_xor(lane_sum, o, 64);
-              if (lane == 0) gS[gi] = double(lane_sum) * (1.0 / Q);
+              const float bsum = wave_sum(lane_sum);
+              if (lane == 0) gS[gi] = double(bsum) * (1.0 / Q);
               wave_sync();
               continue;
             }
@@ -709,20 +765,8 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
                   img[(ty * T + rr) * STRIDE + tx * T + cc] = g[rr][cc];
               s = g[0][0];
             }
-            // levels above the tile, unscaled: the four tiles of a block of side
-            // 2 ht tiles are lanes l, l ^ ht, l ^ ht TS and l ^ (ht TS + ht)
-#pragma unroll
-            for (int ht = 1; ht < TS; ht <<= 1) {
-              const float b = __shfl_xor(s, ht, 64);
-              const float c = __shfl_xor(s, ht * TS, 64);
-              const float d = __shfl_xor(s, ht * TS + ht, 64);
-              if (owns_tile && ((tx | ty) & (2 * ht - 1)) == 0) {
-                img[(ty * T) * STRIDE + (tx + ht) * T] = (s - b) + (c - d);
-                img[((ty + ht) * T) * STRIDE + tx * T] = (s + b) - (c + d);
-                img[((ty + ht) * T) * STRIDE + (tx + ht) * T] = (s - b) - (c - d);
-                s = (s + b) + (c + d);
-              }
-            }
+            // levels above the tile, unscaled
+            if constexpr (TS > 1) tile_level_above<1, TS, T, STRIDE>(s, img, lane, tx, ty, owns_tile);
             // the block's orthonormal scaling coefficient, for the levels above
             if (lane == 0) gS[gi] = double(s) * (1.0 / Q);
             wave_sync();
