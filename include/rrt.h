@@ -99,7 +99,7 @@ const char* rrt_last_error(void);
  * one per face; a longitude-latitude map 2).
  *   pix, coef: [squares][n][n] float32, may not overlap.
  *   squares >= 0 (0 = no-op), 1 <= n <= 1024, n a power of two.
- *   No workspace: for n > 128 the work is split into 128 x 128 tiles plus
+ *   No workspace: for n > 64 the work is split into 64 x 64 tiles plus
  *   one coarse pass, and the tile sums between the two launches are staged
  *   in the output buffer itself.
  * --------------------------------------------------------------------- */

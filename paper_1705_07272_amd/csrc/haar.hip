@@ -2,12 +2,13 @@
 // H/V/D coefficients of every scale are finite differences of 2x2 block
 // averages of the next finer scale; Mallat quadrant layout per face).
 //
-// Each face is cut into Q x Q tiles (Q = min(n, 128)), one 256-thread
-// workgroup per tile: the tile is staged in LDS, the levels of block side
-// 2..Q are computed in place there (S stays at the block's corner), and the
-// H/V/D outputs of every level go straight to their Mallat positions, which
-// for one tile form contiguous row segments.  For n > 128 the (n/128)^2 tile
-// sums are combined by a second, tiny launch; the tile sums travel between
+// Each face is cut into Q x Q tiles (Q = min(n, 64)), one 256-thread
+// workgroup per tile: the tile is staged in LDS (16 KiB, small enough to run
+// beside relight waves that hold most of a CU's LDS), the levels of block
+// side 2..Q are computed in place there (S stays at the block's corner), and
+// the H/V/D outputs of every level go straight to their Mallat positions,
+// which for one tile form contiguous row segments.  For n > 64 the (n/64)^2
+// tile sums are combined by a second, tiny launch; the tile sums travel between
 // the launches through the top-left corner of the output (forward) or the
 // first texel of each output tile (inverse), positions no other coefficient
 // or texel of the first launch uses.
@@ -19,7 +20,8 @@ namespace rrt {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTile = 128;
+constexpr int kTile = 64;
+constexpr int kMaxGrid = 1024 / kTile;  // tiles per face side at n = 1024
 
 __device__ __forceinline__ void butterfly(float a, float b, float c, float d, float& S, float& H,
                                           float& V, float& D) {
@@ -76,9 +78,9 @@ __global__ __launch_bounds__(kThreads) void haar_fwd_tiles(const float* __restri
 
 // Coarse levels above the tiles: the G x G tile sums sit in the top-left
 // corner of each face of `coef` (spatial order); they are replaced by their
-// own Mallat transform.  grid: count * 6; LDS: G * G floats (G <= 8).
+// own Mallat transform.  grid: count * 6; LDS: G * G floats (G <= kMaxGrid).
 __global__ __launch_bounds__(64) void haar_fwd_coarse(float* __restrict__ coef, int n, int G) {
-  __shared__ float s[64];
+  __shared__ float s[kMaxGrid * kMaxGrid];
   float* f = coef + int64_t(blockIdx.x) * n * n;
   for (int e = threadIdx.x; e < G * G; e += 64) s[e] = f[int64_t(e / G) * n + (e % G)];
   __syncthreads();
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(64) void haar_fwd_coarse(float* __restrict__ coef, 
 // the tile sum of tile (ty, tx) to stage[face * n * n + ty * rs + tx * cs].
 __global__ __launch_bounds__(64) void haar_inv_coarse(const float* coef, float* stage, int n,
                                                       int G, int64_t rs, int64_t cs) {
-  __shared__ float s[64];
+  __shared__ float s[kMaxGrid * kMaxGrid];
   const float* f = coef + int64_t(blockIdx.x) * n * n;
   float* st = stage + int64_t(blockIdx.x) * n * n;
   if (threadIdx.x == 0) s[0] = f[0];
@@ -226,7 +228,7 @@ int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, h
   return check_launch("haar_inv_tiles");
 }
 
-// `coef` is the caller's own dense staging buffer: for n > 128 its Mallat
+// `coef` is the caller's own dense staging buffer: for n > 64 its Mallat
 // corner is overwritten by the tile sums (spatial order).
 int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
                             hipStream_t s, bool strips) {

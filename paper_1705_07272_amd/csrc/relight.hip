@@ -273,10 +273,13 @@ __device__ __forceinline__ void tile_levels(float (&g)[T][T]) {
   }
 }
 
-// Row stride of a wave's Q x Q block image in LDS: padded by 8 floats for
-// Q >= 16 so that the 8 rows of an 8 x 8 patch, and the 8 tiles read by 8
-// lanes, fall in distinct banks.
-constexpr int image_stride(int Q) { return Q >= 16 ? Q + 8 : Q; }
+// Row stride of a wave's Q x Q block image in LDS.  Unpadded at Q = 32: a
+// wave then needs 6.8 KiB of LDS, and the 20 waves a CU holds (the register
+// limit) leave 25 KiB free for the preparation kernels of the next lighting
+// to run beside the relight (the image's stores and tile reads take 2- to
+// 4-way bank conflicts instead, a small cost on the LDS pipe).  Q = 16 keeps
+// 8 floats of padding.
+constexpr int image_stride(int Q) { return Q == 16 ? Q + 8 : Q; }
 // Key of a block entry: log2 of its block side (3 bits), block number
 // (13 bits) and image offset (11 bits, < 32 * 40).
 constexpr int kOffBits = 11;
