@@ -250,17 +250,21 @@ __global__ __launch_bounds__(kChunkThreads) void tk_hist(const float* __restrict
   for (int b = tid; b < kBins; b += kChunkThreads) out[b] = h[b];
 }
 
-// The single-workgroup steps of a long row run with kSmallThreads so that
-// they find room on a CU next to other work (a 1024-thread workgroup needs
-// 16 free wave slots on one CU at once).
+// The single-workgroup steps of a long row run as four waves (one per SIMD)
+// of at most 32 VGPRs with dynamic LDS, so that they find room on a CU next
+// to other work (a relight kernel holding 5 waves of 96 VGPRs per SIMD
+// leaves 32 per SIMD).
 constexpr int kSmallThreads = 256;
+#define RRT_SMALL_STEP __global__ __launch_bounds__(kSmallThreads)
 
-__global__ __launch_bounds__(kSmallThreads) void tk_bin(const uint32_t* __restrict__ hist,
-                                                        int chunks, int k,
-                                                        uint32_t* __restrict__ eq_base,
-                                                        uint32_t* __restrict__ par) {
+RRT_SMALL_STEP void tk_bin(const uint32_t* __restrict__ hist, int chunks, int k,
+                           uint32_t* __restrict__ eq_base, uint32_t* __restrict__ par) {
   constexpr int kWaves = kSmallThreads / 64;
   constexpr int kPer = kBins / kSmallThreads;
+  // per-bin totals in dynamic LDS (kBins words): with a static array the
+  // compiler pads the register allocation to the occupancy the LDS allows,
+  // which keeps the wave from running beside other kernels
+  extern __shared__ unsigned tot[];
   __shared__ int sh[kWaves];
   __shared__ int s_bin, s_need;
   const int tid = threadIdx.x, row = blockIdx.x;
@@ -269,26 +273,32 @@ __global__ __launch_bounds__(kSmallThreads) void tk_bin(const uint32_t* __restri
     s_need = 0;
   }
   const uint32_t* h = hist + int64_t(row) * chunks * kBins;
-  unsigned tot[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) tot[j] = 0;
-  for (int c = 0; c < chunks; ++c)
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) tot[j] += h[int64_t(c) * kBins + kPer * tid + j];
+  // per-bin totals over the chunks (each thread owns bins tid + 64 j)
+#pragma unroll 1
+  for (int b = tid; b < kBins; b += kSmallThreads) {
+    unsigned t = 0;
+#pragma unroll 4
+    for (int c = 0; c < chunks; ++c) t += h[int64_t(c) * kBins + b];
+    tot[b] = t;
+  }
+  __syncthreads();
+  // this thread's bins kPer tid .. kPer tid + kPer - 1
+  const unsigned* mt = tot + kPer * tid;
   int mine = 0;
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) mine += int(tot[j]);
+#pragma unroll 4
+  for (int j = 0; j < kPer; ++j) mine += int(mt[j]);
   int total;
   const int before = block_scan<kWaves>(mine, &total, sh);
   // keys in bins above this thread's bins
   unsigned above = unsigned(total - before - mine);
-#pragma unroll
+#pragma unroll 4
   for (int j = kPer - 1; j >= 0; --j) {
-    if (above < unsigned(k) && above + tot[j] >= unsigned(k)) {
+    const unsigned c = mt[j];
+    if (above < unsigned(k) && above + c >= unsigned(k)) {
       s_bin = kPer * tid + j;
       s_need = int(unsigned(k) - above);
     }
-    above += tot[j];
+    above += c;
   }
   __syncthreads();
   const int bin = s_bin;
@@ -363,7 +373,7 @@ __global__ __launch_bounds__(kChunkThreads) void tk_cand(const float* __restrict
       });
 }
 
-__global__ __launch_bounds__(kSmallThreads) void tk_resolve(int64_t len,
+RRT_SMALL_STEP void tk_resolve(int64_t len,
                                                             const uint32_t* __restrict__ ckey,
                                                             const int32_t* __restrict__ cidx,
                                                             uint32_t* __restrict__ par) {
@@ -507,7 +517,8 @@ int launch_topk(const float* x, int64_t rows, int64_t len, int k, int32_t* idx, 
     const dim3 grid(unsigned(cp.chunks), unsigned(rows));
     hipLaunchKernelGGL(tk_hist, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
                        w.hist);
-    hipLaunchKernelGGL(tk_bin, dim3(unsigned(rows)), dim3(kSmallThreads), 0, s, w.hist, cp.chunks, k,
+    hipLaunchKernelGGL(tk_bin, dim3(unsigned(rows)), dim3(kSmallThreads), kBins * sizeof(unsigned), s,
+                       w.hist, cp.chunks, k,
                        w.eq_base, w.par);
     hipLaunchKernelGGL(tk_cand, grid, dim3(kChunkThreads), 0, s, x, len, cp.chunk_len, cp.chunks,
                        w.eq_base, w.par, w.ckey, w.cidx);
