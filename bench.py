@@ -22,7 +22,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.32 T non-packed 32-bit lane-ops/s
+# VALU lane-operations per second: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz =
+# 78.6 T (the published 157.3 TFLOP/s FP32 vector rate with an FMA counted as
+# two flops).  A wave64 instruction issues in 2 cycles at that rate; many
+# instructions (three-operand, cube-map, conversion) take 4 and v_rcp_f32 8,
+# so the rate an instruction mix reaches lies below this peak.
+PEAK_ALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 # Algorithmic operations per rotated texel: the gfx950 instructions the
 # exact source map, the gather and the texel's share of the 2x2 levels need

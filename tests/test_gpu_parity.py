@@ -51,7 +51,8 @@ def check_frames(got, ref_scale, tol=TOL_F32, rel_l2=True):
 
 
 # ---------------------------------------------------------------- Haar (a1, a3)
-@pytest.mark.parametrize("n,count", [(1, 2), (2, 3), (8, 1), (32, 2), (128, 1), (256, 2), (512, 1)])
+@pytest.mark.parametrize("n,count", [(1, 2), (2, 3), (8, 1), (32, 2), (64, 3), (128, 1), (256, 2),
+                                     (512, 1), (1024, 1)])
 def test_haar_forward_inverse(rrt, n, count):
     from oracle.haar import haar_forward, haar_inverse
     rng = np.random.default_rng(n + count)
