@@ -476,9 +476,11 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
   constexpr int NF = LL ? 2 : 6;  // faces (squares) of the map
   // Blocks holding no listed entry of their own only feed the levels above
   // them through their sum: with SUM_ONLY such a block skips the image, the
-  // levels inside it and the entry scan (not for CHAIN, whose image holds
-  // level-1 coefficients, nor BRDF, whose factor applies in the tile phase).
-  constexpr bool SUM_ONLY = !CHAIN && !BRDF;
+  // levels inside it and the entry scan (with CHAIN it also skips the chain
+  // rule: a 2x2 block's texels sum to twice its scaling coefficient, which
+  // the rule takes from the source block unchanged; not for BRDF, whose
+  // factor applies in the tile phase).
+  constexpr bool SUM_ONLY = !BRDF;
   constexpr int TS = Q >= 8 ? 8 : Q;  // tiles per block side
   constexpr int T = Q / TS;           // texels per tile side
   constexpr int LOGQ = __builtin_ctz(Q);
@@ -660,6 +662,19 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
               const __amdgpu_buffer_rsrc_t blk = __builtin_amdgcn_make_buffer_rsrc(
                   const_cast<float4*>(p.blocks), short(0), 6 * hn * hn * 16, kBufferWord3);
               const float3 rb = dir_mad(ax.mU, float(2 * (Q / 2) * bx), ax.mV, float(2 * (Q / 2) * by), h0);
+              if (SUM_ONLY && !full) {
+                // only the block's sum: twice the source blocks' S
+                float sv[2][2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                  for (int b = 0; b < 2; ++b) {
+                    const float3 d = dir_mad(ax.mU, float(16 * b), ax.mV, float(16 * a), rb);
+                    const unsigned at = source_texel_scaled<4>(d.x, d.y, d.z, logn - 1);
+                    sv[a][b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(blk, int(at), 0, 0));
+                  }
+                lane_sum = 2.0f * ((sv[0][0] + sv[0][1]) + (sv[1][0] + sv[1][1]));
+              } else {
               float4 cf[2][2];
               int sf[2][2];
 #pragma unroll
@@ -689,6 +704,7 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
                   img[(r0 + 1) * STRIDE + c0] = o.z;
                   img[(r0 + 1) * STRIDE + c0 + 1] = o.w;
                 }
+              }
             } else if (owns_tile) {
             // Gather in TS x TS patches of adjacent texels (one load instruction
             // covers a compact patch, which the L1 serves with few cache lines):
