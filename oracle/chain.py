@@ -35,7 +35,8 @@ Discrete reading on the cube map (texel units: texel (i, j) spans
   its four pixels follow by the inverse 2x2 step, and every coarser level by
   the pyramid.
 
-R is the quantised rotation R_q / 2^20, the matrix the exact map uses.
+R is the quantised rotation R_q / 2^k (k = scale_bits(n)), the matrix the exact
+map uses.
 """
 import numpy as np
 

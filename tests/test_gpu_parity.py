@@ -277,7 +277,8 @@ def test_relight_frames_composition(rrt):
 
 
 def test_relight_n256_regions(rrt):
-    """n = 256: four 128 x 128 regions per face and the levels above them."""
+    """n = 256: 8 x 8 blocks of 32 x 32 per face, the FP64 levels above them, and
+    the source map written by 64 x 64 inverse-Haar tiles plus their coarse pass."""
     from cases import build_case, reference, workload
     w = workload(302, 256, 2048, 6, 256, exp_lo=1.0, exp_hi=8.0)   # low exponents: 5 faces
     case = build_case(w)
