@@ -249,6 +249,49 @@ __device__ __forceinline__ unsigned latlong_source(const LLTab& t, int i, int jc
   return (unsigned(col >> logh) << (2 * logh)) + (unsigned(row) << logh) + unsigned(col & (H - 1));
 }
 
+// The same rule for a compile-time H = 2^LOGH: the two searches unroll, the
+// table offsets become immediates and the searches of a lane's texels can
+// be interleaved.
+template <int LOGH>
+__device__ __forceinline__ unsigned latlong_source_h(const LLTab& t, int i, int jc, float cb,
+                                                     float sb, int sa) {
+#pragma clang fp contract(off)
+  constexpr int H = 1 << LOGH;
+  const float px = t.rs[i] * t.cs[jc];
+  const float py = t.rc[i];
+  const float pz = t.rs[i] * t.cc[jc];
+  const float qy = cb * py - sb * pz;
+  const float qz = sb * py + cb * pz;
+  const float rho = __fsqrt_rn(px * px + qz * qz);
+  int row = 0, c = 0;
+#pragma unroll
+  for (int step = H >> 1; step >= 1; step >>= 1) {
+    row += (qy <= t.bnd[row + step]) ? step : 0;
+    c += (qz <= t.bnd[c + step] * rho) ? step : 0;
+  }
+  int col = px >= 0.0f ? c : 2 * H - 1 - c;
+  col = (col + sa) & (2 * H - 1);
+  return (unsigned(col >> LOGH) << (2 * LOGH)) + (unsigned(row) << LOGH) + unsigned(col & (H - 1));
+}
+
+// A lane's T x T gathered texels of block (by, bx) of square `face` through
+// the longitude-latitude rule at H = 2^LOGH.
+template <int LOGH, int Q, int TS, int T, typename SrcT>
+__device__ __forceinline__ void latlong_gather(float (&val)[T][T], const LLTab& tab,
+                                               __amdgpu_buffer_rsrc_t src, int face, int by,
+                                               int bx, int ty, int tx, float cb, float sb, int sa,
+                                               int sc) {
+  constexpr int n = 1 << LOGH;
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      const int i = by * Q + TS * a + ty;
+      const int jc = (face * n + bx * Q + TS * b + tx + sc) & (2 * n - 1);
+      val[a][b] = load_src<SrcT>(src, latlong_source_h<LOGH>(tab, i, jc, cb, sb, sa));
+    }
+}
+
 // Unscaled 2x2 levels with block side 2..T inside a thread's T x T tile, in
 // place (S stays at the block corner, H/V/D at the corner + B/2 offsets):
 // S' = (a + b) + (c + d), H' = (a - b) + (c - d), V' = (a + b) - (c + d),
@@ -637,15 +680,35 @@ __global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
               // the same compact patches, through the lat-long rule
               if (owns_tile) {
                 float val[T][T];
+                // H below 32 has Q = H; from 32 on, Q = 32 and H = 32 .. 512
+                if constexpr (Q < 32) {
+                  latlong_gather<LOGQ, Q, TS, T, SrcT>(val, tab, src, face, by, bx, ty, tx, llcb,
+                                                       llsb, llsa, llsc);
+                } else {
+                  switch (logn) {
+#define RRT_LL_CASE(L)                                                                         \
+  case L:                                                                                      \
+    latlong_gather<L, Q, TS, T, SrcT>(val, tab, src, face, by, bx, ty, tx, llcb, llsb, llsa, \
+                                      llsc);                                                   \
+    break;
+                    RRT_LL_CASE(5)
+                    RRT_LL_CASE(6)
+                    RRT_LL_CASE(7)
+                    RRT_LL_CASE(8)
+                    RRT_LL_CASE(9)
+#undef RRT_LL_CASE
+                    default:
 #pragma unroll
-                for (int a = 0; a < T; ++a)
+                      for (int a = 0; a < T; ++a)
 #pragma unroll
-                  for (int b = 0; b < T; ++b) {
-                    const int i = by * Q + TS * a + ty;
-                    const int jc = (face * n + bx * Q + TS * b + tx + llsc) & (2 * n - 1);
-                    val[a][b] = load_src<SrcT>(
-                        src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa));
+                        for (int b = 0; b < T; ++b) {
+                          const int i = by * Q + TS * a + ty;
+                          const int jc = (face * n + bx * Q + TS * b + tx + llsc) & (2 * n - 1);
+                          val[a][b] = load_src<SrcT>(
+                              src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa));
+                        }
                   }
+                }
                 if (full) {
 #pragma unroll
                   for (int a = 0; a < T; ++a)
