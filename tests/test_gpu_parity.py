@@ -518,7 +518,7 @@ def test_latlong_grid_tables_exact(rrt, H):
 @pytest.mark.parametrize("H,V,nnz,k,comp", [(4, 9, 20, 32, False), (8, 17, 64, 128, False),
                                             (16, 23, 128, 256, True), (32, 31, 256, 1024, False),
                                             (64, 29, 256, 1024, False), (128, 19, 256, 1024, True),
-                                            (256, 7, 256, 2048, False)])
+                                            (256, 7, 256, 2048, False), (512, 3, 256, 2048, False)])
 def test_relight_latlong(rrt, H, V, nnz, k, comp):
     """Lat-long relighting against the checker's binary32 rule + FP64 levels
     and dot on the same stored inputs."""
