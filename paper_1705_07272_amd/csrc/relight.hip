@@ -514,8 +514,12 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
 // rotated texels are multiplied by the vertex's BRDF factor (not with CHAIN).
 // LL: the map is a longitude-latitude map (two squares, one frame, the
 // elevation-plus-shift rotation of latlong_source) instead of a cube map.
+// The chain-rule variant is held to 5 waves per SIMD (96 VGPRs, a few
+// spilled): 0.430 -> 0.411 ms on the benchmark launch against 4 waves
+// unspilled; the lat-long variant held to 6 waves spills more and runs
+// slower, so it keeps its 5.
 template <int Q, typename SrcT, bool CHAIN, bool BRDF, bool LL>
-__global__ __launch_bounds__(kThreads) void relight_kernel(RelightParams p) {
+__global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(RelightParams p) {
   constexpr int NF = LL ? 2 : 6;  // faces (squares) of the map
   // Blocks holding no listed entry of their own only feed the levels above
   // them through their sum: with SUM_ONLY such a block skips the image, the
