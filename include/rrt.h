@@ -58,7 +58,9 @@
 extern "C" {
 #endif
 
-#define RRT_ABI_VERSION 2
+/* 3: rotations quantised at 2^(22 - log2 n) instead of 2^20 (same calls,
+   slightly different source texels for general rotations). */
+#define RRT_ABI_VERSION 3
 
 typedef enum {
   RRT_OK = 0,

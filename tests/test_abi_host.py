@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(rrt):
 
 def test_version_and_strings(rrt):
     lib = rrt.lib
-    assert lib.rrt_abi_version() == 2
+    assert lib.rrt_abi_version() == 3
     assert lib.rrt_status_string(0) == b"ok"
     assert lib.rrt_status_string(3) == b"workspace too small"
     assert lib.rrt_status_string(99) == b"unknown status"
