@@ -75,6 +75,45 @@ def blocks_to_pixels(B):
     return P
 
 
+def gnomonic_jacobian(c, cx, cy, h):
+    """Derivatives of the source texel coordinates x' = h (sc / D + 1),
+    y' = h (tc / D + 1) along the destination texel axes x and y.
+
+    c = (sc, tc, D): in-face and major components of the direction for the
+    source face at the point; cx, cy: their derivatives along x and y, which
+    are constant (the direction is linear in the destination coordinates).
+    Quotient rule on s = sc / D:
+        s_x  = (sc_x D - sc D_x) / D^2,
+        s_xy = 2 sc D_x D_y / D^3 - (sc_x D_y + sc_y D_x) / D^2,
+    and likewise for t = tc / D.  Returns (x'_x, x'_y, y'_x, y'_y, x'_xy, y'_xy)."""
+    sc, tc, D = c
+    scx, tcx, Dx = cx
+    scy, tcy, Dy = cy
+    xx = h * (scx * D - sc * Dx) / D**2
+    xy = h * (scy * D - sc * Dy) / D**2
+    yx = h * (tcx * D - tc * Dx) / D**2
+    yy = h * (tcy * D - tc * Dy) / D**2
+    xxy = h * (2 * sc * Dx * Dy / D**3 - (scx * Dy + scy * Dx) / D**2)
+    yxy = h * (2 * tc * Dx * Dy / D**3 - (tcx * Dy + tcy * Dx) / D**2)
+    return xx, xy, yx, yy, xxy, yxy
+
+
+def block_jacobian(R, F, sface, U, V, n):
+    """gnomonic_jacobian at destination points (U, V) of face F (U = 2x - n,
+    V = 2y - n in texel units) for the rotation R (float [3, 3]) and the
+    source face `sface` (arrays broadcast together)."""
+    mU, mV, mN = (R @ FACE_AXES[F][k] for k in range(3))
+    U = np.asarray(U, np.float64)
+    V = np.asarray(V, np.float64)
+    d = U[..., None] * mU + V[..., None] * mV + n * mN       # [..., 3]
+    dx, dy = 2.0 * mU, 2.0 * mV                               # d per texel step in x, y
+    sel = FACE_AXES[sface]                                    # source face: rows eU, eV, eN
+    c = tuple(np.einsum("...k,...k->...", sel[..., r, :], d) for r in range(3))
+    cx = tuple(np.einsum("...k,k->...", sel[..., r, :], dx) for r in range(3))
+    cy = tuple(np.einsum("...k,k->...", sel[..., r, :], dy) for r in range(3))
+    return gnomonic_jacobian(c, cx, cy, n // 2)
+
+
 def chain_rotate(P, Rq):
     """Rotated map [6, n, n] with the finest level rotated by the chain rule."""
     P = np.asarray(P, dtype=np.float64)
@@ -89,19 +128,7 @@ def chain_rotate(P, Rq):
     V = (4 * bi + 2 - n).astype(np.float64)
     out = np.empty((6, h, h, 4))
     for F in range(6):
-        mU, mV, mN = (R @ FACE_AXES[F][k] for k in range(3))
-        d = U[..., None] * mU + V[..., None] * mV + n * mN    # [h, h, 3]
-        dx, dy = 2.0 * mU, 2.0 * mV                           # d per texel step in x, y
-        sel = FACE_AXES[sface[F]]                             # source face: rows eU, eV, eN
-        sc, tc, D = (np.einsum("ijk,ijk->ij", sel[..., r, :], d) for r in range(3))
-        scx, tcx, Dx = (np.einsum("ijk,k->ij", sel[..., r, :], dx) for r in range(3))
-        scy, tcy, Dy = (np.einsum("ijk,k->ij", sel[..., r, :], dy) for r in range(3))
-        xx = h * (scx * D - sc * Dx) / D**2
-        xy = h * (scy * D - sc * Dy) / D**2
-        yx = h * (tcx * D - tc * Dx) / D**2
-        yy = h * (tcy * D - tc * Dy) / D**2
-        xxy = h * (2 * sc * Dx * Dy / D**3 - (scx * Dy + scy * Dx) / D**2)
-        yxy = h * (2 * tc * Dx * Dy / D**3 - (tcx * Dy + tcy * Dx) / D**2)
+        xx, xy, yx, yy, xxy, yxy = block_jacobian(R, F, sface[F], U, V, n)
         S, H, Vf, Df = (Bf[F][..., k] for k in range(4))
         fx, fy, fxy = -H, -Vf, 2 * Df
         gx = fx * xx + fy * yx
