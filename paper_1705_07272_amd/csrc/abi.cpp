@@ -29,13 +29,7 @@ int check_launch(const char* what) {
 
 static bool valid_n(int n, int lo) { return n >= lo && n <= 1024 && is_pow2(n); }
 
-// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float|half];
-// after prepare the staging area holds the chain rule's 6 (n/2)^2 float4 blocks.
-struct RelightWs {
-  size_t dense_off, src_off, total;
-};
-
-static RelightWs relight_ws(int n, bool f16) {
+RelightWs relight_ws(int n, bool f16) {
   const size_t cells = size_t(6) * n * n;
   RelightWs w;
   w.dense_off = 0;
@@ -62,7 +56,7 @@ static int check_ws(const void* ws, size_t ws_bytes, size_t need, const char* wh
   return RRT_OK;
 }
 
-static int validate_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T) {
+int validate_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T) {
   if (!L || !R || !T) return fail(RRT_ERR_INVALID, "relight: null descriptor");
   const int vs = validate_light(L);
   if (vs) return vs;
@@ -211,8 +205,11 @@ int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_
   return RRT_OK;
 }
 
-static int check_relight_flags(const rrt_light* L, unsigned flags,
-                               const rrt_transport* T = nullptr) {
+}  // extern "C"
+
+namespace rrt {
+
+int check_relight_flags(const rrt_light* L, unsigned flags, const rrt_transport* T) {
   if (flags & ~(RRT_COMPENSATED | RRT_CHAIN_RULE))
     return fail(RRT_ERR_INVALID, "relight: unknown flags 0x%x", flags);
   if ((flags & RRT_CHAIN_RULE) && L->n < 32)
@@ -221,6 +218,10 @@ static int check_relight_flags(const rrt_light* L, unsigned flags,
     return fail(RRT_ERR_UNSUPPORTED, "relight: chain rule with a brdf (triple product)");
   return RRT_OK;
 }
+
+}  // namespace rrt
+
+extern "C" {
 
 int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_bytes,
                         void* stream) {

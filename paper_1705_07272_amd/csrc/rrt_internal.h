@@ -23,6 +23,17 @@ inline int ilog2(int64_t x) {
 }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float|half];
+// after prepare the staging area holds the chain rule's 6 (n/2)^2 float4 blocks.
+struct RelightWs {
+  size_t dense_off, src_off, total;
+};
+RelightWs relight_ws(int n, bool f16);
+// Host-side validation of rrt_relight's descriptors and flags (abi.cpp); a
+// non-zero return has recorded the message for rrt_last_error().
+int validate_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T);
+int check_relight_flags(const rrt_light* L, unsigned flags, const rrt_transport* T = nullptr);
+
 // Haar transform launchers (haar.hip).
 // squares: number of n x n squares (a cube map is 6, a longitude-latitude map 2)
 int launch_haar_forward(const float* pix, float* coef, int n, int64_t squares, hipStream_t s);
