@@ -4,6 +4,12 @@ Thin torch-facing binding of librrt.so: every function checks and marshals
 its tensor arguments and calls the C ABI of include/rrt.h; all arithmetic
 runs in the library's HIP kernels.  torch provides device memory and the
 current stream only.
+
+Every function checks the shapes of its tensors against the sizes it passes
+to the library (vertex count, row length, block count, frame count, ...)
+before it checks devices or calls into the library, and raises ValueError on
+a mismatch: the kernels index their buffers by those sizes, so a tensor of
+the wrong shape would otherwise be read or written out of bounds.
 """
 import ctypes
 
@@ -40,6 +46,66 @@ def _dev(t, name, dtype=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _numel(t, name, count):
+    """t (a tensor, or None) holds exactly `count` elements."""
+    if t is not None and t.numel() != count:
+        raise ValueError(f"{name} has shape {tuple(t.shape)} ({t.numel()} elements), "
+                         f"expected {count} elements")
+
+
+def _rows(t, name, rows, cols):
+    """t is [rows, cols] (a 1-D tensor stands for one row)."""
+    if t is None:
+        return
+    shape = tuple(t.shape)
+    ok = (t.dim() == 2 and shape == (rows, cols)) or (t.dim() == 1 and rows == 1 and shape == (cols,))
+    if not ok:
+        raise ValueError(f"{name} has shape {shape}, expected ({rows}, {cols})")
+
+
+def _rotations(t, name):
+    """[count, 3, 3] or [count, 9] rotations -> count."""
+    if t.dim() == 0 or t.numel() != 9 * t.shape[0]:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (count, 3, 3)")
+    return t.shape[0]
+
+
+def _nblk(nnz):
+    return (nnz + RRT_BLOCK - 1) // RRT_BLOCK
+
+
+def _transport_shapes(nvert, t_idx, t_val, block_scale, cluster=None, brdf=None, material=None,
+                      order=None, n=None, squares=6):
+    """Shapes of a transport given as tensors; returns nnz."""
+    if t_val.dim() not in (1, 2):
+        raise ValueError(f"transport_val has shape {tuple(t_val.shape)}, expected (V, nnz)")
+    nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
+    _rows(t_val, "transport_val", nvert, nnz)
+    if cluster is not None:
+        _numel(cluster, "cluster", nvert)
+        if t_idx is None or t_idx.dim() != 2 or t_idx.shape[1] != nnz:
+            raise ValueError("with cluster, transport_idx must be a support table (C, nnz) "
+                             f"with nnz = {nnz}")
+    elif t_idx is not None:
+        _rows(t_idx, "transport_idx", nvert, nnz)
+    if t_val.dtype in (torch.uint8, torch.int16):
+        if block_scale is None:
+            raise ValueError("block-scaled transport (uint8 / int16 codes) needs block_scale")
+        _rows(block_scale, "block_scale", nvert, _nblk(nnz))
+    if brdf is not None:
+        if n is None or brdf.dim() == 0 or brdf.numel() != brdf.shape[0] * squares * n * n:
+            raise ValueError(f"brdf has shape {tuple(brdf.shape)}, expected (M, {squares}, n, n)")
+        _numel(material, "material", nvert)
+    _numel(order, "order", nvert)
+    return nnz
+
+
+def _light_shapes(light_idx, light_val):
+    if light_idx.dim() != 1 or tuple(light_val.shape) != tuple(light_idx.shape):
+        raise ValueError(f"light_idx {tuple(light_idx.shape)} and light_val "
+                         f"{tuple(light_val.shape)} must be the same 1-D shape")
+
+
 def _ptr_or_null(t, name, dtype=None):
     return ctypes.c_void_p(0) if t is None else _dev(t, name, dtype)
 
@@ -51,11 +117,19 @@ def _workspace(nbytes, device):
     return ws
 
 
+def _square(t, name):
+    """[..., n, n] -> n."""
+    if t.dim() < 2 or t.shape[-1] != t.shape[-2]:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., n, n)")
+    return t.shape[-1]
+
+
 def haar_forward(pix, out=None):
     """Haar transform of every n x n square of [..., n, n] float32 (cube maps
     [..., 6, n, n], lat-long maps [..., 2, H, H])."""
-    n = pix.shape[-1]
+    n = _square(pix, "pix")
     count = pix.numel() // (n * n) if pix.numel() else 0
+    _numel(out, "out", pix.numel())
     out = torch.empty_like(pix) if out is None else out
     check(lib.rrt_haar_forward(_dev(pix, "pix", torch.float32), _dev(out, "out", torch.float32),
                                n, count, _stream()))
@@ -63,8 +137,9 @@ def haar_forward(pix, out=None):
 
 
 def haar_inverse(coef, out=None):
-    n = coef.shape[-1]
+    n = _square(coef, "coef")
     count = coef.numel() // (n * n) if coef.numel() else 0
+    _numel(out, "out", coef.numel())
     out = torch.empty_like(coef) if out is None else out
     check(lib.rrt_haar_inverse(_dev(coef, "coef", torch.float32), _dev(out, "out", torch.float32),
                                n, count, _stream()))
@@ -75,15 +150,23 @@ def topk(x, k, out=None, workspace=None):
     """Row-wise k largest |x| -> (idx int32 ascending, values) for x [rows, len].
     out: optional (idx, val) tensors to fill; workspace: optional device
     buffer of at least rrt_topk_workspace() bytes."""
+    if x.dim() != 2:
+        raise ValueError(f"x has shape {tuple(x.shape)}, expected (rows, len)")
     rows, length = x.shape
+    if not 0 <= k <= length:
+        raise ValueError(f"k={k} not in [0, {length}]")
     if out is None:
         idx = torch.empty((rows, k), dtype=torch.int32, device=x.device)
         val = torch.empty((rows, k), dtype=torch.float32, device=x.device)
     else:
         idx, val = out
+        _numel(idx, "idx", rows * k)
+        _numel(val, "val", rows * k)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_topk_workspace(rows, length, k, ctypes.byref(nbytes)))
     ws = _workspace(nbytes.value, x.device) if workspace is None else workspace
+    if ws.dtype != torch.uint8:
+        raise TypeError("workspace must be a uint8 tensor")
     check(lib.rrt_topk(_dev(x, "x", torch.float32), rows, length, k, _dev(idx, "idx", torch.int32),
                        _dev(val, "val", torch.float32), _dev(ws, "ws"), ws.numel(), _stream()))
     return idx, val
@@ -106,8 +189,10 @@ def coarsen_indices(idx, n, levels):
 
 def haar_phase_shift(coef, rot):
     """Dense Haar-domain rotation of one cube map [6, n, n] by rot [r, 3, 3]."""
-    n = coef.shape[-1]
-    nrot = rot.shape[0]
+    n = _square(coef, "coef")
+    if tuple(coef.shape) != (6, n, n):
+        raise ValueError(f"coef has shape {tuple(coef.shape)}, expected (6, n, n)")
+    nrot = _rotations(rot, "rot")
     out = torch.empty((nrot, 6, n, n), dtype=torch.float32, device=coef.device)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_haar_phase_shift_workspace(n, nrot, ctypes.byref(nbytes)))
@@ -119,7 +204,12 @@ def haar_phase_shift(coef, rot):
 
 
 def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
-                 cluster=None, brdf=None, material=None, order=None):
+                 cluster=None, brdf=None, material=None, order=None, out=None):
+    _light_shapes(light_idx, light_val)
+    nvert = _rotations(vert_rot, "vert_rot")
+    nframes = 1 if frame_rot is None else _rotations(frame_rot, "frame_rot")
+    _numel(out, "out", nframes * nvert)
+    _transport_shapes(nvert, t_idx, t_val, block_scale, cluster, brdf, material, order, n)
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -173,13 +263,15 @@ def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, blo
     order [V] int32: processing order of the vertices (relight_order), or None.
     """
     L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
-                           cluster, brdf, material, order)
+                           cluster, brdf, material, order, out)
     flags = _flags(compensated, chain_rule)
     nbytes = ctypes.c_size_t(0)
     check(lib.rrt_relight_workspace(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), flags,
                                     ctypes.byref(nbytes)))
     if workspace is None:
         workspace = _workspace(nbytes.value, vert_rot.device)
+    if workspace.dtype != torch.uint8:
+        raise TypeError("workspace must be a uint8 tensor")
     if out is None:
         out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
     check(lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
@@ -202,6 +294,7 @@ class PreparedLighting:
 
 
 def prepare_lighting(n, light_idx, light_val, workspace=None, chain_rule=False):
+    _light_shapes(light_idx, light_val)
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -212,6 +305,8 @@ def prepare_lighting(n, light_idx, light_val, workspace=None, chain_rule=False):
                                     0, ctypes.byref(nbytes)))
     if workspace is None:
         workspace = _workspace(nbytes.value, light_idx.device)
+    if workspace.dtype != torch.uint8:
+        raise TypeError("workspace must be a uint8 tensor")
     check(lib.rrt_relight_prepare(ctypes.byref(L), _flags(False, chain_rule),
                                   _dev(workspace, "workspace"), workspace.numel(), _stream()))
     return PreparedLighting(n, light_idx, light_val, workspace, chain_rule)
@@ -223,7 +318,7 @@ def relight_prepared(prep, vert_rot, t_idx, t_val, frame_rot=None, block_scale=N
     """relight() with a lighting already reconstructed by prepare_lighting()
     (the chain rule applies when the lighting was prepared for it)."""
     L, R, T = _descriptors(prep.n, prep.light_idx, prep.light_val, vert_rot, t_idx, t_val,
-                           frame_rot, block_scale, cluster, brdf, material, order)
+                           frame_rot, block_scale, cluster, brdf, material, order, out)
     if out is None:
         out = torch.empty((R.nframes, T.nvert), dtype=torch.float32, device=vert_rot.device)
     check(lib.rrt_relight_prepared(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
@@ -241,6 +336,12 @@ def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_sc
     light_idx [k] int32 / light_val [k] float32|float16 over [2, H, H];
     elev [V, 2] float32 (cos b, sin b); shift [V, 2] int32 (s_a, s_c);
     t_idx [V, nnz] int32 or None (dense), t_val [V, nnz] as for relight()."""
+    _light_shapes(light_idx, light_val)
+    if elev.dim() != 2 or elev.shape[1] != 2:
+        raise ValueError(f"elev has shape {tuple(elev.shape)}, expected (V, 2)")
+    _rows(shift, "shift", elev.shape[0], 2)
+    _transport_shapes(elev.shape[0], t_idx, t_val, block_scale)
+    _numel(out, "out", elev.shape[0])
     L = Light(H, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -257,6 +358,8 @@ def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_sc
     check(lib.rrt_relight_latlong_workspace(ctypes.byref(L), ctypes.byref(nbytes)))
     if workspace is None:
         workspace = _workspace(nbytes.value, elev.device)
+    if workspace.dtype != torch.uint8:
+        raise TypeError("workspace must be a uint8 tensor")
     if out is None:
         out = torch.empty(nvert, dtype=torch.float32, device=elev.device)
     check(lib.rrt_relight_latlong(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
@@ -272,6 +375,16 @@ def relight_mlp(n, light_idx, light_val, vert_rot, weights, bias, supports, scal
     weights RRT_MLP_WEIGHT_COUNT bfloat16, bias RRT_MLP_BIAS_COUNT float32,
     supports [C, 256] int32, scales [C, 256] float32, pos_nrm [V, 6]
     float32, cluster [V] int32."""
+    _light_shapes(light_idx, light_val)
+    _mlp_shapes(weights, bias)
+    if supports.dim() != 2 or supports.shape[1] != RRT_MLP_OUT:
+        raise ValueError(f"supports has shape {tuple(supports.shape)}, expected (C, {RRT_MLP_OUT})")
+    _rows(scales, "scales", supports.shape[0], RRT_MLP_OUT)
+    nvert = _rotations(vert_rot, "vert_rot")
+    _rows(pos_nrm, "pos_nrm", nvert, 6)
+    _numel(cluster, "cluster", nvert)
+    nframes = 1 if frame_rot is None else _rotations(frame_rot, "frame_rot")
+    _numel(out, "out", nframes * nvert)
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -287,6 +400,8 @@ def relight_mlp(n, light_idx, light_val, vert_rot, weights, bias, supports, scal
                                         ctypes.byref(nbytes)))
     if workspace is None:
         workspace = _workspace(nbytes.value, pos_nrm.device)
+    if workspace.dtype != torch.uint8:
+        raise TypeError("workspace must be a uint8 tensor")
     if out is None:
         out = torch.empty((nframes, nvert), dtype=torch.float32, device=pos_nrm.device)
     check(lib.rrt_relight_mlp(ctypes.byref(L), ctypes.byref(R), ctypes.byref(M),
@@ -313,10 +428,15 @@ def relight_order(n, t_idx, cluster=None, out=None, workspace=None, nvert=None, 
     (or, with cluster [V], support rows t_idx [C, nnz]) over 6 n^2
     coefficients (rrt_relight_order); t_idx None means nvert dense rows."""
     if t_idx is None:
+        if nvert is None:
+            raise ValueError("dense rows (t_idx None) need nvert")
         V, nnz, dev_ = nvert, 6 * n * n, torch.device(device)
     else:
-        V = t_idx.shape[0] if cluster is None else cluster.shape[0]
+        if t_idx.dim() != 2:
+            raise ValueError(f"t_idx has shape {tuple(t_idx.shape)}, expected (rows, nnz)")
+        V = t_idx.shape[0] if cluster is None else cluster.numel()
         nnz, dev_ = t_idx.shape[-1], t_idx.device
+    _numel(out, "order", V)
     dummy = torch.empty(1, dtype=torch.int32, device=dev_)
     L = Light(n, 1, dummy.data_ptr(), dummy.data_ptr(), RRT_F32)
     T = Transport(V, nnz, _ptr_or_null(t_idx, "t_idx", torch.int32).value, None, RRT_F32, None,
@@ -350,6 +470,8 @@ def project_rows(pix, nnz):
 def convert(x, dtype):
     """Storage conversion of a [rows, cols] float32 tensor: 'f16', 'bf16',
     'e4m3' or 's16' (the last two return (codes, block scales float32))."""
+    if x.dim() != 2:
+        raise ValueError(f"x has shape {tuple(x.shape)}, expected (rows, cols)")
     rows, cols = x.shape
     if dtype == "f16":
         out = torch.empty((rows, cols), dtype=torch.float16, device=x.device)
@@ -379,8 +501,15 @@ from ._abi import (RRT_MLP_BIAS_COUNT, RRT_MLP_HIDDEN, RRT_MLP_IN, RRT_MLP_OUT, 
                    RRT_MLP_WEIGHT_COUNT)
 
 
+def _mlp_shapes(w, bias):
+    _numel(w, "weights", RRT_MLP_WEIGHT_COUNT)
+    _numel(bias, "bias", RRT_MLP_BIAS_COUNT)
+
+
 def mlp_encode(pos_nrm):
     """[B, 6] float32 -> [B, 128] bfloat16 positional encoding."""
+    if pos_nrm.dim() != 2 or pos_nrm.shape[1] != 6:
+        raise ValueError(f"pos_nrm has shape {tuple(pos_nrm.shape)}, expected (B, 6)")
     B = pos_nrm.shape[0]
     x = torch.empty((B, RRT_MLP_IN), dtype=torch.bfloat16, device=pos_nrm.device)
     check(lib.rrt_mlp_encode(_dev(pos_nrm, "pos_nrm", torch.float32), B, _dev(x, "x"), _stream()))
@@ -395,7 +524,11 @@ def mlp_workspace(B, device):
 
 def mlp_forward(w_bf16, bias, x, workspace=None, out=None):
     """out [B, 256] float32 for packed bfloat16 weights and float32 biases."""
+    _mlp_shapes(w_bf16, bias)
+    if x.dim() != 2 or x.shape[1] != RRT_MLP_IN:
+        raise ValueError(f"x has shape {tuple(x.shape)}, expected (B, {RRT_MLP_IN})")
     B = x.shape[0]
+    _numel(out, "out", B * RRT_MLP_OUT)
     workspace = mlp_workspace(B, x.device) if workspace is None else workspace
     out = torch.empty((B, RRT_MLP_OUT), dtype=torch.float32, device=x.device) if out is None else out
     check(lib.rrt_mlp_forward(_dev(w_bf16, "w", torch.bfloat16), _dev(bias, "bias", torch.float32),
@@ -406,7 +539,13 @@ def mlp_forward(w_bf16, bias, x, workspace=None, out=None):
 
 def mlp_backward(w_bf16, x, dout, workspace, dw=None, db=None):
     """(dw [294912], db [1280]) float32; workspace from the forward pass."""
+    _numel(w_bf16, "weights", RRT_MLP_WEIGHT_COUNT)
+    if x.dim() != 2 or x.shape[1] != RRT_MLP_IN:
+        raise ValueError(f"x has shape {tuple(x.shape)}, expected (B, {RRT_MLP_IN})")
     B = x.shape[0]
+    _numel(dout, "dout", B * RRT_MLP_OUT)
+    _numel(dw, "dw", RRT_MLP_WEIGHT_COUNT)
+    _numel(db, "db", RRT_MLP_BIAS_COUNT)
     dw = torch.empty(RRT_MLP_WEIGHT_COUNT, dtype=torch.float32, device=x.device) if dw is None else dw
     db = torch.empty(RRT_MLP_BIAS_COUNT, dtype=torch.float32, device=x.device) if db is None else db
     check(lib.rrt_mlp_backward(_dev(w_bf16, "w", torch.bfloat16), _dev(x, "x", torch.bfloat16), B,
@@ -418,6 +557,9 @@ def mlp_backward(w_bf16, x, dout, workspace, dw=None, db=None):
 
 def mse(out, target, dout=None, loss=None):
     """(dout, loss) with loss a device float64 scalar tensor (accumulated)."""
+    _numel(target, "target", out.numel())
+    _numel(dout, "dout", out.numel())
+    _numel(loss, "loss", 1)
     dout = torch.empty_like(out) if dout is None else dout
     loss = torch.zeros((), dtype=torch.float64, device=out.device) if loss is None else loss
     check(lib.rrt_mse(_dev(out, "out", torch.float32), _dev(target, "target", torch.float32),
@@ -427,6 +569,8 @@ def mse(out, target, dout=None, loss=None):
 
 
 def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, param_bf16=None):
+    for t, name in ((grad, "grad"), (m, "m"), (v, "v"), (param_bf16, "param_bf16")):
+        _numel(t, name, param.numel())
     check(lib.rrt_adam_step(_dev(param, "param", torch.float32),
                             _ptr_or_null(param_bf16, "param_bf16", torch.bfloat16),
                             _dev(m, "m", torch.float32), _dev(v, "v", torch.float32),
