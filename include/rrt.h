@@ -205,6 +205,26 @@ int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_
 int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
                 float* radiance, unsigned flags, void* ws, size_t ws_bytes, void* stream);
 
+/* rrt_relight without caller memory, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, validation, kernels
+   and results as rrt_relight; the workspace is instead a device array of
+   RRT_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the
+   first use until the process ends (looked up once per device, with that
+   device current).  It uses the current device's array, so `stream` must
+   belong to the current device.  The call allocates nothing and never
+   calls hipMalloc / hipFree.
+     Limit: the relight workspace of rrt_relight_workspace() must fit the
+   array: n <= 256 (n = 512 and 1024 return RRT_ERR_UNSUPPORTED before any
+   HIP call).
+     Every call on a GPU shares that GPU's array: calls that overlap in time
+   on one GPU (on different streams, or from different threads without
+   ordering) race and give unspecified results; calls ordered on one stream
+   are safe.  Nothing depends on what an earlier call left in the array. */
+#define RRT_NOALLOC_SCRATCH_BYTES (4u << 20)
+int rrt_relight_noalloc(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
+                        float* radiance, unsigned flags, void* stream);
+
 /* Processing order for rrt_relight: the vertices sorted by the number of
    cube faces their rows touch, most first (a vertex's work grows with it),
    so that the expensive vertices do not start last.  Within a face count

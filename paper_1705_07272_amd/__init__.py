@@ -21,6 +21,7 @@ from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M
                    lib)
 
 __all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight",
+           "relight_noalloc",
            "relight_latlong", "relight_mlp", "relight_order", "mlp_encode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
@@ -277,6 +278,22 @@ def relight(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot=None, blo
     check(lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
                           _dev(out, "out", torch.float32), flags, _dev(workspace, "workspace"),
                           workspace.numel(), _stream()))
+    return out
+
+
+def relight_noalloc(n, light_idx, light_val, vert_rot, t_idx, t_val, out, frame_rot=None,
+                    block_scale=None, compensated=False, cluster=None, chain_rule=False,
+                    brdf=None, material=None, order=None):
+    """relight() through rrt_relight_noalloc: no workspace and no allocation,
+    the caller passes the output out [F, V] float32.  The library's scratch
+    array holds the workspace (n <= 256); calls that overlap on one GPU race."""
+    if out is None:
+        raise ValueError("relight_noalloc writes into a caller-provided out [F, V]")
+    L, R, T = _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, block_scale,
+                           cluster, brdf, material, order, out)
+    check(lib.rrt_relight_noalloc(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
+                                  _dev(out, "out", torch.float32),
+                                  _flags(compensated, chain_rule), _stream()))
     return out
 
 

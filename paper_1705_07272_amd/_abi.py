@@ -24,6 +24,8 @@ RRT_BLOCK = 64
 RRT_COMPENSATED = 1
 RRT_CHAIN_RULE = 2
 
+RRT_NOALLOC_SCRATCH_BYTES = 4 << 20
+
 RRT_MLP_IN = 128
 RRT_MLP_HIDDEN = 256
 RRT_MLP_OUT = 256
@@ -84,6 +86,8 @@ SIGNATURES = {
     "rrt_relight": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint, c_void_p,
                             c_size_t, c_void_p]),
     "rrt_relight_prepare": (c_int, [P(Light), c_uint, c_void_p, c_size_t, c_void_p]),
+    "rrt_relight_noalloc": (c_int, [P(Light), P(Rotations), P(Transport), c_void_p, c_uint,
+                                    c_void_p]),
     "rrt_relight_latlong_workspace": (c_int, [P(Light), P(c_size_t)]),
     "rrt_relight_order_workspace": (c_int, [c_int64, P(c_size_t)]),
     "rrt_relight_order": (c_int, [P(Light), P(Transport), c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -159,6 +159,33 @@ def test_relight_validation(rrt):
                                     None) == E.RRT_ERR_UNSUPPORTED
 
 
+def test_relight_noalloc_validation(rrt):
+    """Every rejection of the no-allocation relight happens before its first
+    HIP call (no GPU here): the relight's own checks, then the scratch limit
+    (n <= 256: the n = 512 workspace is 12 MiB against 4 MiB)."""
+    E = rrt._abi
+    lib = rrt.lib
+
+    def call(L, R, T, out=8, flags=0):
+        return lib.rrt_relight_noalloc(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T),
+                                       _p(out), flags, None)
+
+    assert E.RRT_NOALLOC_SCRATCH_BYTES == 4 << 20
+    for n in (512, 1024):
+        assert call(*_desc(rrt, n=n)) == E.RRT_ERR_UNSUPPORTED
+        assert b"scratch" in lib.rrt_last_error()
+    assert _relight_ws(rrt, *_desc(rrt, n=256))[1] <= E.RRT_NOALLOC_SCRATCH_BYTES
+    assert _relight_ws(rrt, *_desc(rrt, n=512, ldtype=E.RRT_F16))[1] > E.RRT_NOALLOC_SCRATCH_BYTES
+    assert call(*_desc(rrt, n=3)) == E.RRT_ERR_INVALID
+    assert call(*_desc(rrt, nframes=2)) == E.RRT_ERR_INVALID
+    assert call(*_desc(rrt), out=0) == E.RRT_ERR_INVALID                   # null radiance
+    assert call(*_desc(rrt), flags=4) == E.RRT_ERR_INVALID                 # unknown flag
+    assert call(*_desc(rrt), flags=E.RRT_CHAIN_RULE) == E.RRT_ERR_UNSUPPORTED   # n < 32
+    L, R, T = _desc(rrt)
+    assert lib.rrt_relight_noalloc(None, ctypes.byref(R), ctypes.byref(T), _p(8), 0,
+                                   None) == E.RRT_ERR_INVALID
+
+
 def test_convert_validation(rrt):
     lib = rrt.lib
     E = rrt._abi
