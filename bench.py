@@ -69,63 +69,77 @@ def kernel_fingerprint():
 
 
 # ----------------------------------------------------------------------------
-# CPU baseline: the FP64 checker timed on host cores over a bounded sample.
+# CPU baseline and accuracy clause: the FP64 checker on the GPU's own stored
+# inputs for a bounded vertex sample, timed on the host cores; its result is
+# also the reference of the timed GPU output on that sample.
 # ----------------------------------------------------------------------------
-def _cpu_prep(args):
-    cfg, vids = args
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    from oracle.relight import transport_rows
-    from scenes.scene import WORKLOADS, phong_exponents, transport_pixels
-    w = WORKLOADS[cfg]
-    exps = phong_exponents(w)
-    with threadpool_limits(limits=1):     # one core per worker process
-        idx, val = transport_rows(transport_pixels(w, exps[vids], vids), w.nnz)
-    return np.asarray(vids), idx, val
-
-
 def _cpu_relight(args):
     light_idx, light_val, n, rot, frame_rot, idx, val = args
     from threadpoolctl import threadpool_limits
 
     from oracle.relight import relight
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=1):     # one core per worker process
         return relight(light_idx, light_val, n, rot, frame_rot, idx, val)
 
 
-def cpu_baseline(cfg, sample, workers):
-    import multiprocessing as mp
+def host_cores():
+    """Cores of this job: the process's CPU affinity, at most the 16 cores a
+    one-GPU job is given on the benchmark machines."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
+
+def _cpu_warm(_):
+    import oracle.relight  # noqa: F401  (imported before the timed region)
+    from threadpoolctl import threadpool_limits  # noqa: F401
+    return os.getpid()
+
+
+def start_cpu_pool(workers):
+    """Worker processes forked before any device work in this process, with
+    the checker's modules already imported in each."""
+    import multiprocessing as mp
+    pool = mp.get_context("fork").Pool(workers)
+    pool.map(_cpu_warm, range(4 * workers))
+    return pool
+
+
+def cpu_baseline(pool, workers, inputs, got, label):
+    """inputs = (light_idx, light_val, n, vert_rot [S, 3, 3], frame_rot,
+    t_idx [S, nnz], t_val [S, nnz]): host copies of the device's stored
+    lighting and rows of the S sampled vertices, bit for bit (FP32 values).
+    got [F, S]: the timed device radiance of those vertices.  Returns the
+    baseline record, the max frame rel-L2 of got against the checker and the
+    checker's radiance [F, S]."""
     import numpy as np
 
-    from oracle.relight import lighting_coefficients
-    from scenes.scene import WORKLOADS, frame_rotations, lighting_pixels, vertex_rotations
-    w = WORKLOADS[cfg]
-    rng = np.random.default_rng(12345)
-    vids = np.sort(rng.choice(w.nverts, size=min(sample, w.nverts), replace=False))
-    chunks = [c for c in np.array_split(vids, workers * 4) if len(c)]
-    li, lv = lighting_coefficients(lighting_pixels(cfg, w.n), w.k_light)
-    rot = vertex_rotations(w)
-    frot = frame_rotations(w)
-    frames = 1 if frot is None else frot.shape[0]
-    ctx = mp.get_context("fork")       # before any device work in this process
-    with ctx.Pool(workers) as pool:
-        prepped = pool.map(_cpu_prep, [(cfg, c) for c in chunks])
-        jobs = [(li, lv, w.n, rot[v], frot, i, x) for v, i, x in prepped]
-        t0 = time.perf_counter()
-        pool.map(_cpu_relight, jobs)
-        dt = time.perf_counter() - t0
-    # one process on one core, on the first chunk
-    t1 = time.perf_counter()
+    from oracle.relight import rel_l2
+    li, lv, n, rot, frot, idx, val = inputs
+    S = rot.shape[0]
+    chunks = [c for c in np.array_split(np.arange(S), workers * 4) if len(c)]
+    jobs = [(li, lv, n, rot[c], frot, idx[c], val[c]) for c in chunks]
+    t0 = time.perf_counter()
+    ref = np.concatenate(pool.map(_cpu_relight, jobs), axis=1)
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()          # one process on one core, the first chunk
     _cpu_relight(jobs[0])
     dt1 = time.perf_counter() - t1
-    return {"value": round(len(vids) * frames / dt, 3), "unit": "relit vertices/s",
+    frames = ref.shape[0]
+    err = max(rel_l2(got[f], ref[f]) for f in range(frames))
+    base = {"value": round(S * frames / dt, 3), "unit": "relit vertices/s",
             "cores": workers, "kind": "oracle",
-            "single_core_value": round(len(jobs[0][5]) * frames / dt1, 3),
-            "sample": f"{len(vids)} seeded vertices x {frames} frame(s) of {w.name}, FP64 "
-                      f"pixel rotate + Haar + dense dot, {workers} single-threaded processes, "
-                      f"{dt:.1f} s wall"}
+            "single_core_value": round(len(chunks[0]) * frames / dt1, 3),
+            "sample": f"{S} seeded vertices x {frames} frame(s) of {label}, the device's stored "
+                      f"lighting and rows (FP32), FP64 pixel rotate + Haar + dense dot, "
+                      f"{workers} single-threaded processes, {dt:.1f} s wall"}
+    return base, err, ref
+
+
+def accuracy_sample(nverts, frames, budget):
+    """Seeded vertex sample of about `budget` vertex-frames (at least 64
+    vertices), sorted."""
+    import numpy as np
+    count = min(nverts, max(64, budget // frames))
+    return np.sort(np.random.default_rng(12345).choice(nverts, size=count, replace=False))
 
 
 # ----------------------------------------------------------------------------
@@ -161,17 +175,18 @@ def device_inputs(w, form, batch=2048, materials=0):
         val[s:e] = v
         del T
     scale = None
+    val32 = val                        # the FP32 stored rows the forms are made from
     if form == "bf16":
         val = rrt.convert(val, "bf16")
-    elif form in ("e4m3", "s16"):
+    elif form in ("e4m3", "s16", "s11"):
         val, scale = rrt.convert(val, form)
     brdf = mat = None
     if materials:
         brdf = torch.from_numpy(brdf_pixels(w, materials).astype(np.float32)).to(dev)
         mat = torch.from_numpy(material_ids(w, materials)).to(dev)
     torch.cuda.synchronize()
-    return dict(pix=pix, rot=rot, frot=frot, idx=idx, val=val, scale=scale, brdf=brdf,
-                material=mat)
+    return dict(pix=pix, rot=rot, frot=frot, idx=idx, val=val, val32=val32, scale=scale,
+                brdf=brdf, material=mat)
 
 
 def run_latlong(args):
@@ -253,128 +268,235 @@ def run_latlong(args):
 
 
 def run_learned(args, w):
-    """Learned-decoder form on the displaced-sphere workload: setup (k-means,
-    supports, targets, device training, held-out error against the stored
-    per-vertex rows) untimed; the timed step is a1-a2 + rrt_relight_mlp
-    (reconstruction, decode, relight in one library call)."""
+    """Learned-decoder form on the displaced-sphere scene (6 x 256^2, top-2,048
+    lighting; the 200,000-vertex training mesh, or with --workload 5 the same
+    surface at 1,000,000 vertices x 64 frames).  Setup, untimed: k-means (64
+    clusters), cluster supports, targets, device training.  Accuracy on a
+    seeded sample of vertices the network never saw, each against the FP64
+    checker fed the device's stored per-vertex rows (timed as the CPU
+    baseline): the stored rows relit on the device, the exact coefficients
+    on the cluster supports (the support floor: what a perfect network
+    would reach) and the decoder.  Timed: the learned step (a1-a2 +
+    rrt_relight_mlp, decode and relight in one call) and, on the same scene,
+    the plain FP32 stored-rows step (a1-a2 + rrt_relight)."""
     import numpy as np
     import torch
 
     import paper_1705_07272_amd as rrt
+    from oracle.relight import rel_l2
     from paper_1705_07272_amd import learned
     from scenes.mesh import (displaced_sphere, learned_transport_pixels_torch, mesh_inputs,
                              tangent_frames)
-    from scenes.scene import lighting_pixels
+    from scenes.scene import WORKLOADS, frame_rotations, lighting_pixels
+    wt = WORKLOADS[4]                  # the training mesh
     t0 = time.perf_counter()
-    p, nrm, u, rho = displaced_sphere(w.cfg, w.nverts)
+    p, nrm, u, rho = displaced_sphere(wt.cfg, wt.nverts)
     frames = tangent_frames(nrm)
     feats = mesh_inputs(p, nrm)
-    _, labels = learned.kmeans(feats, 64, iters=25, seed=1)
+    centres, labels = learned.kmeans(feats, 64, iters=25, seed=1)
 
-    def pixels(ids):
-        ids = np.asarray(ids)
-        return learned_transport_pixels_torch(w.n, p[ids], frames[ids], u[ids], rho[ids], "cuda",
-                                              dtype=torch.float32)
+    def pixels_of(P, FR, U, RHO):
+        def pixels(ids):
+            ids = np.asarray(ids)
+            return learned_transport_pixels_torch(w.n, P[ids], FR[ids], U[ids], RHO[ids], "cuda",
+                                                  dtype=torch.float32)
+        return pixels
 
+    pixels = pixels_of(p, frames, u, rho)
     supports, scales = learned.cluster_supports(pixels, labels, 64, w.nnz, sample_per_cluster=256)
-    perm = np.random.default_rng(7).permutation(w.nverts)
-    held, train = np.sort(perm[: w.nverts // 10]), np.sort(perm[w.nverts // 10:])
+    perm = np.random.default_rng(7).permutation(wt.nverts)
+    held, train = np.sort(perm[: wt.nverts // 10]), np.sort(perm[wt.nverts // 10:])
     targets = learned.targets_on_supports(pixels, train, labels, supports)
     dec = learned.TransportDecoder(supports, scales, seed=3)
-    f_all = torch.from_numpy(feats)
-    lab_all = torch.from_numpy(labels.astype(np.int32))
-    hist = dec.train(f_all[train], targets, lab_all[train], steps=args.mlp_steps, batch=4096,
-                     lr=2e-3, log_every=max(1, args.mlp_steps // 10))
+    hist = dec.train(torch.from_numpy(feats)[train], targets,
+                     torch.from_numpy(labels.astype(np.int32))[train], steps=args.mlp_steps,
+                     batch=4096, lr=2e-3, log_every=max(1, args.mlp_steps // 10))
     del targets
     print(f"learned setup {time.perf_counter() - t0:.1f} s, loss {hist[0][1]:.3e} -> "
           f"{hist[-1][1]:.3e}", file=sys.stderr, flush=True)
 
+    # the relit scene: the training mesh itself, or the same surface sampled
+    # densely (its vertices take the nearest k-means centre's cluster)
+    if w.nverts != wt.nverts:
+        p, nrm, u, rho = displaced_sphere(wt.cfg, w.nverts)
+        frames = tangent_frames(nrm)
+        feats = mesh_inputs(p, nrm)
+        X = feats.astype(np.float64)
+        labels = np.concatenate([np.argmin((np.sum(X[s:s + 65536] ** 2, 1)[:, None]
+                                            - 2.0 * X[s:s + 65536] @ centres.T
+                                            + np.sum(centres ** 2, 1)[None]), axis=1)
+                                 for s in range(0, w.nverts, 65536)])
+        pixels = pixels_of(p, frames, u, rho)
+        unseen = np.arange(w.nverts)
+    else:
+        unseen = held
+    V = w.nverts
     dev = torch.device("cuda")
     pix = torch.from_numpy(lighting_pixels(w.cfg, w.n)).to(dev)
     rot = torch.from_numpy(frames.astype(np.float32)).to(dev)
-    feats_dev = f_all.to(dev)
-    lab_dev = lab_all.to(dev)
-    ws = torch.empty(2 * 6 * w.n * w.n * 4 + 512, dtype=torch.uint8, device=dev)
-    out = torch.empty((1, w.nverts), dtype=torch.float32, device=dev)
+    frot = frame_rotations(w) if w.nframes > 1 else None
+    frot_d = None if frot is None else torch.from_numpy(frot).to(dev)
+    F = 1 if frot is None else frot.shape[0]
+    feats_dev = torch.from_numpy(feats).to(dev)
+    lab_dev = torch.from_numpy(labels.astype(np.int32)).to(dev)
 
-    # held-out error of the decoder against the stored per-vertex rows
+    # stored per-vertex rows (the plain path's input), projected on the device
+    idx = torch.empty((V, w.nnz), dtype=torch.int32, device=dev)
+    val = torch.empty((V, w.nnz), dtype=torch.float32, device=dev)
+    for s in range(0, V, 512):
+        idx[s:s + 512], val[s:s + 512] = rrt.project_rows(pixels(np.arange(s, min(V, s + 512)))
+                                                          .contiguous(), w.nnz)
+    print("stored rows ready", file=sys.stderr, flush=True)
+
+    # accuracy on unseen vertices: stored rows, support floor, decoder
     coef = rrt.haar_forward(pix)
     li, lv = rrt.topk(coef.view(1, -1), w.k_light)
-    prep = rrt.prepare_lighting(w.n, li[0], lv[0], workspace=ws)
-    hold = torch.from_numpy(held).to(dev).long()
-    vals = dec.decode(f_all[held], lab_all[held])
-    r_mlp = rrt.relight_prepared(prep, rot[hold].contiguous(), dec.supports, vals,
-                                 cluster=lab_dev[hold].contiguous())
-    rows_i, rows_v = [], []
-    for s in range(0, len(held), 512):
-        i, v = rrt.project_rows(pixels(held[s:s + 512]).contiguous(), w.nnz)
-        rows_i.append(i)
-        rows_v.append(v)
-    r_rows = rrt.relight_prepared(prep, rot[hold].contiguous(), torch.cat(rows_i), torch.cat(rows_v))
-    err = float(torch.linalg.norm((r_mlp - r_rows).double()) / torch.linalg.norm(r_rows.double()))
-    form = learned.choose_form(err)
+    prep = rrt.prepare_lighting(w.n, li[0], lv[0])
+    vids = np.sort(np.random.default_rng(12345).choice(
+        unseen, size=min(len(unseen), max(64, args.cpu_sample // F)), replace=False))
+    sel = torch.from_numpy(vids).to(dev).long()
+    lab_s = lab_dev[sel].contiguous()
+    ideal = learned.targets_on_supports(pixels, vids, labels, dec.supports)
+    vals = dec.decode(feats_dev[sel].contiguous(), lab_s)
+    kw = dict(frame_rot=frot_d)
+    r_rows = rrt.relight_prepared(prep, rot[sel].contiguous(), idx[sel].contiguous(),
+                                  val[sel].contiguous(), **kw).cpu().numpy()
+    r_ideal = rrt.relight_prepared(prep, rot[sel].contiguous(), dec.supports, ideal.contiguous(),
+                                   cluster=lab_s, **kw).cpu().numpy()
+    r_dec = rrt.relight_prepared(prep, rot[sel].contiguous(), dec.supports, vals,
+                                 cluster=lab_s, **kw).cpu().numpy()
+    base = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        workers = host_cores()
+        pool = start_cpu_pool(workers)
+        inputs = (li[0].cpu().numpy(), lv[0].cpu().numpy(), w.n, rot[sel].cpu().numpy(), frot,
+                  idx[sel].cpu().numpy(), val[sel].cpu().numpy())
+        base, errs["stored_rows"], ref = cpu_baseline(pool, workers, inputs, r_rows, w.name)
+        pool.close()
+        pool.join()
+    else:
+        ref = r_rows.astype(np.float64)   # (no checker run: the device's stored-rows result)
+    fe = lambda x: max(rel_l2(x[f], ref[f]) for f in range(F))  # noqa: E731
+    errs["support_floor"] = fe(r_ideal)
+    errs["decoder"] = fe(r_dec)
+    errs["decoder_vs_floor"] = max(rel_l2(r_dec[f], r_ideal[f]) for f in range(F))
+    form = learned.choose_form(errs["decoder"])
+    print("learned accuracy " + ", ".join(f"{k} {v:.3e}" for k, v in errs.items()),
+          file=sys.stderr, flush=True)
 
-    fused_ws = torch.empty(rrt.relight_mlp_workspace_bytes(w.n, li[0], lv[0], w.nverts),
+    out = torch.empty((F, V), dtype=torch.float32, device=dev)
+    fused_ws = torch.empty(rrt.relight_mlp_workspace_bytes(w.n, li[0], lv[0], V),
                            dtype=torch.uint8, device=dev)
+    ws = torch.empty(2 * 6 * w.n * w.n * 4 + 512, dtype=torch.uint8, device=dev)
+    order = rrt.relight_order(w.n, idx)
 
-    def step(ev=None):
+    def timed(step, nev):
+        for _ in range(args.warmup):
+            step(None)
+        torch.cuda.synchronize()
+        evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(nev))
+               for _ in range(args.steps)]
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(args.steps):
+            step(evs[k])
+        b.record()
+        torch.cuda.synchronize()
+        spans = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps
+                 for i in range(nev - 1)]
+        return a.elapsed_time(b) / args.steps, spans
+
+    def learned_step(ev):
         # a1 + a2, then one library call: reconstruction, decode, relight
         coef = rrt.haar_forward(pix)
         li, lv = rrt.topk(coef.view(1, -1), w.k_light)
         if ev is not None:
             ev[0].record()
-        dec.relight(w.n, li[0], lv[0], rot, feats_dev, lab_dev, out=out, workspace=fused_ws)
+        dec.relight(w.n, li[0], lv[0], rot, feats_dev, lab_dev, frame_rot=frot_d, out=out,
+                    workspace=fused_ws)
         if ev is not None:
             ev[1].record()
 
-    def parts(ev):
-        # the same work as separate calls, for the decode / relight split
+    def stored_step(ev):
         coef = rrt.haar_forward(pix)
         li, lv = rrt.topk(coef.view(1, -1), w.k_light)
         prep = rrt.prepare_lighting(w.n, li[0], lv[0], workspace=ws)
-        ev[0].record()
-        vals = dec.decode(feats_dev, lab_dev)
-        ev[1].record()
-        rrt.relight_prepared(prep, rot, dec.supports, vals, cluster=lab_dev, out=out)
-        ev[2].record()
+        if ev is not None:
+            ev[0].record()
+        rrt.relight_prepared(prep, rot, idx, val, frame_rot=frot_d, out=out, order=order)
+        if ev is not None:
+            ev[1].record()
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2)) for _ in range(args.steps)]
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for k in range(args.steps):
-        step(evs[k])
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / args.steps
-    ms_fused = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    pev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
-    for k in range(args.steps):
-        parts(pev[k])
-    torch.cuda.synchronize()
-    ms_dec = sum(e[0].elapsed_time(e[1]) for e in pev) / args.steps
-    ms_rel = sum(e[1].elapsed_time(e[2]) for e in pev) / args.steps
-    flops = 2.0 * w.nverts * sum(o * i for (o, i) in learned.LAYER_SHAPES)
+    def parts_step(ev):
+        # the learned call's two halves as separate calls: decode, relight
+        coef = rrt.haar_forward(pix)
+        li, lv = rrt.topk(coef.view(1, -1), w.k_light)
+        prep = rrt.prepare_lighting(w.n, li[0], lv[0], workspace=ws)
+        chunk = min(V, 200000)
+        if ev is not None:
+            ev[0].record()
+        vals = dec.decode(feats_dev[:chunk], lab_dev[:chunk])
+        if ev is not None:
+            ev[1].record()
+        rrt.relight_prepared(prep, rot[:chunk], dec.supports, vals, cluster=lab_dev[:chunk],
+                             frame_rot=frot_d)
+        if ev is not None:
+            ev[2].record()
+
+    ms, (ms_mlp_call,) = timed(learned_step, 2)
+    ms_stored, (ms_stored_relight,) = timed(stored_step, 2)
+    _, (ms_dec, ms_rel) = timed(parts_step, 3)
+    chunk = min(V, 200000)
+    flops = 2.0 * chunk * sum(o * i for (o, i) in learned.LAYER_SHAPES)
+    # algorithmic relight work of the decode/relight split: texels of the
+    # faces each vertex's cluster support touches
+    sup_faces = torch.zeros((dec.supports.shape[0], 6), device=dev)
+    sup_faces.scatter_(1, (dec.supports.long() // (w.n * w.n)).clamp(0, 5), 1.0)
+    texels = int(sup_faces.sum(1)[lab_dev[:chunk].long()].sum().item()) * w.n * w.n * F
+    achieved = texels * OPS_PER_TEXEL / (ms_rel * 1e-3) / 1e12
+    dec_tflops = flops / (ms_dec * 1e-3) / 1e12
     print(json.dumps({
         "metric": "relit vertices/s at rel-L2<=1e-3 vs FP64 oracle: plain FP32 vs BF16+MLP",
-        "value": round(w.nverts / (ms * 1e-3), 1), "unit": "relit vertices/s", "n_gpus": 1,
+        "value": round(V * F / (ms * 1e-3), 1), "unit": "relit vertices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 decoder weights/activations, f32 accumulate, f32 relight",
         "data": "synthetic",
-        "config": {"workload": w.name, "cube_face": w.n, "light_coeffs": w.k_light,
-                   "vertices": w.nverts, "clusters": 64, "form": "mlp",
-                   "train_steps": args.mlp_steps},
-        "learned": {"heldout_rel_l2_vs_stored_rows": err, "form_selected": form,
-                    "decoder_bytes": dec.parameter_bytes(),
-                    "stored_rows_bytes_bf16": w.nverts * w.nnz * 6,
-                    "relight_mlp_ms": round(ms_fused, 4),
-                    "decode_ms": round(ms_dec, 4), "relight_ms": round(ms_rel, 4),
-                    "decode_tflops": round(flops / (ms_dec * 1e-3) / 1e12, 2),
-                    "mfma_bf16_peak_tflops": 2500.0},
+        "config": {"workload": w.name if w.nverts == wt.nverts else
+                   f"cube{w.n}_k{w.k_light}_mesh_v{V}_f{F}_mlp",
+                   "cube_face": w.n, "light_coeffs": w.k_light, "vertices": V, "frames": F,
+                   "clusters": 64, "form": "mlp", "train_steps": args.mlp_steps,
+                   "trained_on": wt.name},
+        "accuracy": {"rel_l2": float(f"{errs['decoder']:.4g}"), "bar": 1e-3,
+                     "meets_bar": bool(errs["decoder"] <= 1e-3),
+                     "vertices": int(len(vids)), "frames": F,
+                     "reference": "FP64 oracle on the device's stored per-vertex rows, max "
+                                  "over frames of the rel-L2 over vertices the network never saw",
+                     **{k: float(f"{v:.4g}") for k, v in errs.items()},
+                     "form_selected": form},
+        "stored_rows_fp32": {"value": round(V * F / (ms_stored * 1e-3), 1),
+                             "ms_per_step": round(ms_stored, 4),
+                             "relight_ms": round(ms_stored_relight, 4),
+                             "bytes": V * w.nnz * 8},
+        "learned": {"decoder_bytes": dec.parameter_bytes(),
+                    "relight_mlp_ms": round(ms_mlp_call, 4),
+                    "split_vertices": chunk, "decode_ms": round(ms_dec, 4),
+                    "relight_ms": round(ms_rel, 4),
+                    "workspace_bytes": fused_ws.numel()},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_ALU_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_ALU_TOPS, 4), "traffic": None,
+                     "kernel": "relight_kernel (cluster supports)",
+                     "kernel_ms": round(ms_rel, 4), "rotated_texels": texels,
+                     "ops_per_texel": OPS_PER_TEXEL},
+        "roofline_decode": {"bound": "mfma", "achieved": round(dec_tflops, 2),
+                            "peak": 2500.0, "unit": "TFLOP/s",
+                            "frac": round(dec_tflops / 2500.0, 4),
+                            "kernel": "encode + 5 BF16 MFMA GEMMs + scaling",
+                            "kernel_ms": round(ms_dec, 4), "flops": flops},
+        "cpu_baseline": base,
     }), flush=True)
 
 
@@ -385,7 +507,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2, help="scene configuration (2 = 6x128^2, "
                     "top-1024 lighting, 50,000 vertices, CSR-256 FP32, 1 frame)")
-    ap.add_argument("--form", choices=["f32", "bf16", "s16", "e4m3", "mlp"], default="f32",
+    ap.add_argument("--form", choices=["f32", "bf16", "s16", "s11", "e4m3", "mlp"], default="f32",
                     help="transport storage; the reduced forms also store the lighting in "
                          "binary16 and accumulate with compensation")
     ap.add_argument("--start-level", type=int, default=0,
@@ -425,13 +547,15 @@ def main():
     if args.nnz:
         w = dataclasses.replace(w, nnz=args.nnz)
 
-    base = None
-    # the oracle baseline is of the workload as configured (no budget override)
+    # The checker runs on the exact method's outputs (not the chain-rule or
+    # coarse-start approximations, whose errors the oracle tests measure);
+    # its worker processes start before any device work.
+    pool = workers = None
+    exact = not (args.chain_rule or args.start_level or args.triple)
     if (not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp"
-            and not args.nnz and not args.triple and not args.latlong):
-        workers = max(1, min(16, len(os.sched_getaffinity(0))))
-        base = cpu_baseline(args.workload, args.cpu_sample, workers)
-        print(f"cpu baseline done: {base['sample']}", file=sys.stderr, flush=True)
+            and not args.latlong and exact):
+        workers = host_cores()
+        pool = start_cpu_pool(workers)
 
     import torch
 
@@ -448,7 +572,7 @@ def main():
         return
 
     if args.form == "mlp":
-        run_learned(args, WORKLOADS[4] if args.workload == 2 else w)
+        run_learned(args, WORKLOADS[5] if args.workload == 5 else WORKLOADS[4])
         return
     if args.latlong:
         run_latlong(args)
@@ -534,14 +658,40 @@ def main():
     ms_kernel = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
     ms_prep = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps   # a1-a3 per lighting
 
+    # Accuracy clause of the metric: the timed output of the last step on a
+    # seeded vertex sample against the FP64 checker fed the device's own
+    # stored lighting (its top-K, FP32) and rows (FP32, before any storage
+    # form), bit for bit; the same run times the checker on the host cores.
+    base = accuracy = None
+    if pool is not None:
+        import numpy as np
+        vids = accuracy_sample(V, F, args.cpu_sample)
+        sel = torch.from_numpy(vids).cuda().long()
+        last = (counter[0] - 1) % slots
+        inputs = (lis[last][0].cpu().numpy(), lvs[last][0].cpu().numpy(), n,
+                  inp["rot"][sel].cpu().numpy(),
+                  None if inp["frot"] is None else inp["frot"].cpu().numpy(),
+                  inp["idx"][sel].cpu().numpy(), inp["val32"][sel].cpu().numpy())
+        got = out[:, sel].cpu().numpy()
+        base, err, _ = cpu_baseline(pool, workers, inputs, got, w.name)
+        pool.close()
+        pool.join()
+        bar = 1e-5 if args.form == "f32" else 1e-3
+        accuracy = {"rel_l2": float(f"{err:.4g}"), "bar": bar, "meets_bar": bool(err <= bar),
+                    "vertices": int(len(vids)), "frames": F,
+                    "reference": "FP64 oracle on the device's stored lighting and FP32 rows, "
+                                 "max over frames of the rel-L2 over the sampled vertices"}
+        print(f"accuracy: rel-L2 {err:.3e} on {len(vids)} vertices x {F} frames "
+              f"(bar {bar:g}); {base['sample']}", file=sys.stderr, flush=True)
+
     # algorithmic work of one relight launch
     faces = torch.zeros((V, 7), dtype=torch.float32, device="cuda")
     fid = inp["idx"].long() // (n_rot * n_rot)
     faces.scatter_(1, torch.where(inp["idx"] >= 0, fid, torch.full_like(fid, 6)), 1.0)
     face_count = int((faces[:, :6] > 0).sum().item())
     texels = face_count * n_rot * n_rot * F
-    val_bytes = inp["val"].element_size()
-    hbm_bytes = (V * w.nnz * (4 + val_bytes) + V * 36 + F * V * 4
+    # stored rows: indices, values (packed words for s11), block scales
+    hbm_bytes = (V * w.nnz * 4 + inp["val"].numel() * inp["val"].element_size() + V * 36 + F * V * 4
                  + (0 if inp["scale"] is None else inp["scale"].numel() * 4)
                  + (0 if inp["frot"] is None else F * 36)
                  + (0 if inp["brdf"] is None else inp["brdf"].numel() * 4 + V * 4))
@@ -577,6 +727,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16": "bf16 transport, f16 lighting, f32 accumulate",
                   "s16": "s16 block-scaled transport, f16 lighting, f32 accumulate",
+                  "s11": "packed 11-bit block-scaled transport, f16 lighting, f32 accumulate",
                   "e4m3": "e4m3 transport, f16 lighting, f32 accumulate"}[args.form],
         "data": "synthetic",
         "config": {"workload": w.name, "cube_face": n, "light_coeffs": K, "vertices": V,
@@ -602,9 +753,15 @@ def main():
                      "hbm_algorithmic_bytes": hbm_bytes,
                      "hbm_achieved_gbs": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9, 1),
                      "hbm_peak_gbs": PEAK_HBM_GBS},
+        "accuracy": accuracy,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)
+    # the metric holds at its accuracy bar only: the plain path at 1e-5, the
+    # 16- and 11-bit fixed-point forms at 1e-3 (BF16 and E4M3 cannot meet
+    # 1e-3 on this workload, whatever the arithmetic: their line says so)
+    if accuracy is not None and not accuracy["meets_bar"] and args.form in ("f32", "s16", "s11"):
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -59,8 +59,9 @@ extern "C" {
 #endif
 
 /* 3: rotations quantised at 2^(22 - log2 n) instead of 2^20 (same calls,
-   slightly different source texels for general rotations). */
-#define RRT_ABI_VERSION 3
+   slightly different source texels for general rotations).
+   4: transport dtype RRT_S11 (packed 11-bit block-scaled fixed point). */
+#define RRT_ABI_VERSION 4
 
 typedef enum {
   RRT_OK = 0,
@@ -76,12 +77,22 @@ typedef enum {
   RRT_BF16 = 2,  /* bfloat16 (upper half of binary32) */
   RRT_E4M3 = 3,  /* OCP FP8 E4M3FN (bias 7, max 448, no infinities) with
                     one float32 scale per block of RRT_BLOCK values */
-  RRT_S16 = 4    /* int16 fixed point with one float32 scale per block of
+  RRT_S16 = 4,   /* int16 fixed point with one float32 scale per block of
                     RRT_BLOCK values: value = code * scale */
+  RRT_S11 = 5    /* 11-bit two's-complement fixed point, codes in
+                    [-1023, 1023], one float32 scale per block of RRT_BLOCK
+                    values (value = code * scale), packed: a row of nnz
+                    values is RRT_S11_WORDS(nnz) uint32 words, value e in
+                    bits [11 e, 11 e + 11) of the row's bit stream (bit b in
+                    bit b % 32 of word b / 32); bits past the last value are
+                    zero.  A block of 64 values fills exactly 22 words, so
+                    a row costs 1.4375 bytes per value with its scales. */
 } rrt_dtype;
 
-/* Values per scale block of the block-scaled forms (RRT_E4M3, RRT_S16). */
+/* Values per scale block of the block-scaled forms (RRT_E4M3, RRT_S16, RRT_S11). */
 #define RRT_BLOCK 64
+/* uint32 words of one packed RRT_S11 row of nnz values. */
+#define RRT_S11_WORDS(nnz) ((11 * (int64_t)(nnz) + 31) / 32)
 
 /* Flags of rrt_relight. */
 #define RRT_COMPENSATED 1u  /* Neumaier-compensated accumulation of the dot */
@@ -155,10 +166,11 @@ typedef struct {
   const int32_t* idx;    /* [V][nnz] flat indices in the vertex's local frame,
                             or NULL for dense rows (then nnz must be 6 n^2 and
                             entry e is coefficient e); out-of-range ignored */
-  const void* val;       /* [V][nnz] values of dtype */
-  int dtype;             /* RRT_F32, RRT_BF16, RRT_E4M3 or RRT_S16 */
-  const float* block_scale; /* RRT_E4M3 / RRT_S16: [V][ceil(nnz/64)] scales,
-                            value = code * scale; otherwise ignored */
+  const void* val;       /* [V][nnz] values of dtype ([V][RRT_S11_WORDS(nnz)]
+                            uint32 words for RRT_S11) */
+  int dtype;             /* RRT_F32, RRT_BF16, RRT_E4M3, RRT_S16 or RRT_S11 */
+  const float* block_scale; /* RRT_E4M3 / RRT_S16 / RRT_S11: [V][ceil(nnz/64)]
+                            scales, value = code * scale; otherwise ignored */
   const int32_t* cluster;   /* NULL, or [V] cluster of each vertex: then idx is a
                             per-cluster support table [C][nnz] and vertex v uses
                             row cluster[v] (values stay per vertex);
@@ -288,11 +300,12 @@ int rrt_relight_latlong(const rrt_light* L, const rrt_latlong_rotations* R,
 
 /* ------------------------------------------------------------------------
  * Storage conversion of coefficient values (reduced-precision forms).
- *   src [rows][cols] float32 -> dst [rows][cols] of dtype:
+ *   src [rows][cols] float32 -> dst [rows][cols] of dtype
+ *   ([rows][RRT_S11_WORDS(cols)] uint32 words for RRT_S11):
  *   RRT_F16, RRT_BF16: round to nearest even;
- *   RRT_E4M3, RRT_S16: per block of RRT_BLOCK values of a row, with
- *   m = max|x| of the block and M = 448 (E4M3) or 32767 (S16):
- *   scale = m / M (1 if the block is all zero), stored in
+ *   RRT_E4M3, RRT_S16, RRT_S11: per block of RRT_BLOCK values of a row,
+ *   with m = max|x| of the block and M = 448 (E4M3), 32767 (S16) or 1023
+ *   (S11): scale = m / M (1 if the block is all zero), stored in
  *   block_scale [rows][ceil(cols/64)]; code = round-to-nearest-even of
  *   x * (M / m), saturated to +-M.
  * --------------------------------------------------------------------- */
@@ -345,6 +358,17 @@ int rrt_mlp_workspace(int64_t B, size_t* bytes);
    following rrt_mlp_backward on the same batch. */
 int rrt_mlp_forward(const void* w, const float* bias, const void* x, int64_t B, float* out,
                     void* ws, size_t ws_bytes, void* stream);
+/* Inference of the whole decoder in one kernel, for the transport values of
+   B vertices: values[v][j] = out(encode(pos_nrm[v]))[j] * scale[cluster[v]][j]
+   (0 for a cluster outside [0, nclusters)).  pos_nrm [B][6] float32,
+   cluster [B] int32, scale [nclusters][256] float32, values [B][256]
+   float32.  No workspace: each 256-thread workgroup keeps the activations
+   of 64 vertices in LDS and reads the weights from global memory.  The
+   values are bit-identical to rrt_mlp_encode + rrt_mlp_forward followed
+   by the scaling in binary32. */
+int rrt_mlp_decode(const void* w, const float* bias, const float* scale, int nclusters,
+                   const float* pos_nrm, const int32_t* cluster, int64_t B, float* values,
+                   void* stream);
 /* Gradients of a scalar whose gradient with respect to out is dout [B][256]:
    dw [RRT_MLP_WEIGHT_COUNT] (overwritten), db [RRT_MLP_BIAS_COUNT]
    (overwritten).  ws must hold the activations of rrt_mlp_forward on the
@@ -369,16 +393,19 @@ int rrt_adam_step(float* param, void* param_bf16, float* m, float* v, const floa
  *   {nvert, nnz = RRT_MLP_OUT, idx = support (per-cluster table),
  *   val = values (RRT_F32), cluster, nclusters = C}.
  *   pos_nrm [V][6] float32, cluster [V] int32; radiance [F][V] float32;
- *   flags as rrt_relight.  The decoded values are bit-identical to
- *   rrt_mlp_encode + rrt_mlp_forward + the scaling in binary32; the
- *   vertices are relit in the rrt_relight_order order of their cluster
- *   rows (results unchanged).
- *   Workspace: rrt_relight_mlp_workspace() bytes, 256-byte aligned: the
- *   relight workspace, the decoded values (1 KiB per vertex), one
- *   decoding batch of RRT_MLP_BATCH vertices (activations) and the order
- *   (4 bytes per vertex plus its workspace).
+ *   flags as rrt_relight.  The decoded values are those of rrt_mlp_decode
+ *   (bit-identical to rrt_mlp_encode + rrt_mlp_forward + the scaling in
+ *   binary32); the vertices are relit in the rrt_relight_order order of
+ *   their cluster rows (results unchanged).
+ *   The vertices are processed in chunks of at most RRT_MLP_CHUNK (equal
+ *   sizes): a chunk is decoded (one rrt_mlp_decode launch), ordered and
+ *   relit before the next chunk reuses the same space, so the workspace
+ *   stops growing at V = RRT_MLP_CHUNK: rrt_relight_mlp_workspace() bytes,
+ *   256-byte aligned: the relight workspace, the decoded values of one
+ *   chunk (1 KiB per vertex, 64 MiB at most) and the order of one chunk
+ *   (5 bytes per vertex): about 65 MiB from V = 65,536 on.
  * --------------------------------------------------------------------- */
-#define RRT_MLP_BATCH 16384
+#define RRT_MLP_CHUNK 65536
 typedef struct {
   const void* w;           /* RRT_MLP_WEIGHT_COUNT bfloat16 weights */
   const float* bias;       /* RRT_MLP_BIAS_COUNT float32 biases */

@@ -17,18 +17,25 @@ import torch
 
 from . import _abi
 from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M3, RRT_F16, RRT_F32,  # noqa: F401
-                   RRT_S16, LatLongRotations, Light, Mlp, RrtError, Rotations, Transport, check,
+                   RRT_S11, RRT_S16, LatLongRotations, Light, Mlp, RrtError, Rotations, Transport, check,
                    lib)
 
 __all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight",
            "relight_noalloc",
-           "relight_latlong", "relight_mlp", "relight_order", "mlp_encode",
+           "relight_latlong", "relight_mlp", "relight_order", "mlp_encode", "mlp_decode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
 
 _DTYPES = {torch.float32: RRT_F32, torch.float16: RRT_F16, torch.bfloat16: RRT_BF16,
-           torch.uint8: RRT_E4M3, torch.int16: RRT_S16}
+           torch.uint8: RRT_E4M3, torch.int16: RRT_S16, torch.int32: RRT_S11}
+# dtypes of stored transport values (int32: packed 11-bit words)
+_TRANSPORT_DTYPES = (torch.float32, torch.bfloat16, torch.uint8, torch.int16, torch.int32)
+
+
+def s11_words(nnz):
+    """int32 words of one packed 11-bit row of nnz values (RRT_S11_WORDS)."""
+    return (11 * nnz + 31) // 32
 
 
 def _stream():
@@ -80,8 +87,20 @@ def _transport_shapes(nvert, t_idx, t_val, block_scale, cluster=None, brdf=None,
     """Shapes of a transport given as tensors; returns nnz."""
     if t_val.dim() not in (1, 2):
         raise ValueError(f"transport_val has shape {tuple(t_val.shape)}, expected (V, nnz)")
-    nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
-    _rows(t_val, "transport_val", nvert, nnz)
+    if t_val.dtype == torch.int32:
+        # packed 11-bit rows: nnz comes from the index rows (or the dense map)
+        if t_idx is not None:
+            if t_idx.dim() not in (1, 2):
+                raise ValueError(f"transport_idx has shape {tuple(t_idx.shape)}, expected (V, nnz)")
+            nnz = t_idx.shape[-1]
+        elif n is not None:
+            nnz = squares * n * n
+        else:
+            raise ValueError("packed 11-bit transport needs index rows or the map size")
+        _rows(t_val, "transport_val", nvert, s11_words(nnz))
+    else:
+        nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
+        _rows(t_val, "transport_val", nvert, nnz)
     if cluster is not None:
         _numel(cluster, "cluster", nvert)
         if t_idx is None or t_idx.dim() != 2 or t_idx.shape[1] != nnz:
@@ -89,9 +108,10 @@ def _transport_shapes(nvert, t_idx, t_val, block_scale, cluster=None, brdf=None,
                              f"with nnz = {nnz}")
     elif t_idx is not None:
         _rows(t_idx, "transport_idx", nvert, nnz)
-    if t_val.dtype in (torch.uint8, torch.int16):
+    if t_val.dtype in (torch.uint8, torch.int16, torch.int32):
         if block_scale is None:
-            raise ValueError("block-scaled transport (uint8 / int16 codes) needs block_scale")
+            raise ValueError("block-scaled transport (uint8 / int16 / packed int32 codes) needs "
+                             "block_scale")
         _rows(block_scale, "block_scale", nvert, _nblk(nnz))
     if brdf is not None:
         if n is None or brdf.dim() == 0 or brdf.numel() != brdf.shape[0] * squares * n * n:
@@ -210,7 +230,7 @@ def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, blo
     nvert = _rotations(vert_rot, "vert_rot")
     nframes = 1 if frame_rot is None else _rotations(frame_rot, "frame_rot")
     _numel(out, "out", nframes * nvert)
-    _transport_shapes(nvert, t_idx, t_val, block_scale, cluster, brdf, material, order, n)
+    nnz = _transport_shapes(nvert, t_idx, t_val, block_scale, cluster, brdf, material, order, n)
     L = Light(n, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
               _DTYPES[light_val.dtype])
@@ -218,10 +238,8 @@ def _descriptors(n, light_idx, light_val, vert_rot, t_idx, t_val, frame_rot, blo
     R = Rotations(nframes, _ptr_or_null(frame_rot, "frame_rot", torch.float32).value,
                   _dev(vert_rot, "vert_rot", torch.float32).value)
     nvert = vert_rot.shape[0]
-    nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
     T = Transport(nvert, nnz, _ptr_or_null(t_idx, "transport_idx", torch.int32).value,
-                  _dev(t_val, "transport_val",
-                       (torch.float32, torch.bfloat16, torch.uint8, torch.int16)).value,
+                  _dev(t_val, "transport_val", _TRANSPORT_DTYPES).value,
                   _DTYPES[t_val.dtype],
                   _ptr_or_null(block_scale, "block_scale", torch.float32).value,
                   _ptr_or_null(cluster, "cluster", torch.int32).value,
@@ -357,7 +375,7 @@ def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_sc
     if elev.dim() != 2 or elev.shape[1] != 2:
         raise ValueError(f"elev has shape {tuple(elev.shape)}, expected (V, 2)")
     _rows(shift, "shift", elev.shape[0], 2)
-    _transport_shapes(elev.shape[0], t_idx, t_val, block_scale)
+    nnz = _transport_shapes(elev.shape[0], t_idx, t_val, block_scale, n=H, squares=2)
     _numel(out, "out", elev.shape[0])
     L = Light(H, light_idx.numel(), _dev(light_idx, "light_idx", torch.int32).value,
               _dev(light_val, "light_val", (torch.float32, torch.float16)).value,
@@ -365,10 +383,8 @@ def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_sc
     R = LatLongRotations(_dev(elev, "elev", torch.float32).value,
                          _dev(shift, "shift", torch.int32).value)
     nvert = elev.shape[0]
-    nnz = t_val.shape[-1] if t_val.dim() > 1 else t_val.numel()
     T = Transport(nvert, nnz, _ptr_or_null(t_idx, "transport_idx", torch.int32).value,
-                  _dev(t_val, "transport_val",
-                       (torch.float32, torch.bfloat16, torch.uint8, torch.int16)).value,
+                  _dev(t_val, "transport_val", _TRANSPORT_DTYPES).value,
                   _DTYPES[t_val.dtype], _ptr_or_null(block_scale, "block_scale", torch.float32).value,
                   None, 0, None, None, 0)
     nbytes = ctypes.c_size_t(0)
@@ -486,7 +502,8 @@ def project_rows(pix, nnz):
 
 def convert(x, dtype):
     """Storage conversion of a [rows, cols] float32 tensor: 'f16', 'bf16',
-    'e4m3' or 's16' (the last two return (codes, block scales float32))."""
+    'e4m3', 's16' or 's11' (the last three return (codes, block scales
+    float32); 's11' codes are packed into [rows, s11_words(cols)] int32)."""
     if x.dim() != 2:
         raise ValueError(f"x has shape {tuple(x.shape)}, expected (rows, cols)")
     rows, cols = x.shape
@@ -506,6 +523,13 @@ def convert(x, dtype):
         out = torch.empty((rows, cols), dtype=code_t, device=x.device)
         scale = torch.empty((rows, nblk), dtype=torch.float32, device=x.device)
         check(lib.rrt_convert(_dev(x, "x", torch.float32), rows, cols, code, _dev(out, "out"),
+                              _dev(scale, "scale"), _stream()))
+        return out, scale
+    if dtype == "s11":
+        nblk = (cols + RRT_BLOCK - 1) // RRT_BLOCK
+        out = torch.empty((rows, s11_words(cols)), dtype=torch.int32, device=x.device)
+        scale = torch.empty((rows, nblk), dtype=torch.float32, device=x.device)
+        check(lib.rrt_convert(_dev(x, "x", torch.float32), rows, cols, RRT_S11, _dev(out, "out"),
                               _dev(scale, "scale"), _stream()))
         return out, scale
     raise ValueError(f"unknown dtype {dtype}")
@@ -531,6 +555,27 @@ def mlp_encode(pos_nrm):
     x = torch.empty((B, RRT_MLP_IN), dtype=torch.bfloat16, device=pos_nrm.device)
     check(lib.rrt_mlp_encode(_dev(pos_nrm, "pos_nrm", torch.float32), B, _dev(x, "x"), _stream()))
     return x
+
+
+def mlp_decode(w_bf16, bias, scales, pos_nrm, cluster, out=None):
+    """Decoded transport values [B, 256] float32 (rrt_mlp_decode): the whole
+    network and the per-slot scales of each vertex's cluster in one kernel.
+    scales [C, 256] float32, pos_nrm [B, 6] float32, cluster [B] int32."""
+    _mlp_shapes(w_bf16, bias)
+    if scales.dim() != 2 or scales.shape[1] != RRT_MLP_OUT:
+        raise ValueError(f"scales has shape {tuple(scales.shape)}, expected (C, {RRT_MLP_OUT})")
+    if pos_nrm.dim() != 2 or pos_nrm.shape[1] != 6:
+        raise ValueError(f"pos_nrm has shape {tuple(pos_nrm.shape)}, expected (B, 6)")
+    B = pos_nrm.shape[0]
+    _numel(cluster, "cluster", B)
+    _numel(out, "out", B * RRT_MLP_OUT)
+    out = torch.empty((B, RRT_MLP_OUT), dtype=torch.float32, device=pos_nrm.device) if out is None else out
+    check(lib.rrt_mlp_decode(_dev(w_bf16, "w", torch.bfloat16), _dev(bias, "bias", torch.float32),
+                             _dev(scales, "scales", torch.float32), scales.shape[0],
+                             _dev(pos_nrm, "pos_nrm", torch.float32),
+                             _dev(cluster, "cluster", torch.int32), B,
+                             _dev(out, "out", torch.float32), _stream()))
+    return out
 
 
 def mlp_workspace(B, device):

@@ -19,6 +19,7 @@ RRT_F16 = 1
 RRT_BF16 = 2
 RRT_E4M3 = 3
 RRT_S16 = 4
+RRT_S11 = 5
 RRT_BLOCK = 64
 
 RRT_COMPENSATED = 1
@@ -101,6 +102,8 @@ SIGNATURES = {
     "rrt_convert": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "rrt_mlp_encode": (c_int, [c_void_p, c_int64, c_void_p, c_void_p]),
     "rrt_mlp_workspace": (c_int, [c_int64, P(c_size_t)]),
+    "rrt_mlp_decode": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int64,
+                               c_void_p, c_void_p]),
     "rrt_mlp_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
                                 c_size_t, c_void_p]),
     "rrt_mlp_backward": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,

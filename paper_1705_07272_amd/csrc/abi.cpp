@@ -29,6 +29,13 @@ int check_launch(const char* what) {
 
 static bool valid_n(int n, int lo) { return n >= lo && n <= 1024 && is_pow2(n); }
 
+static bool block_scaled(int dtype) {
+  return dtype == RRT_E4M3 || dtype == RRT_S16 || dtype == RRT_S11;
+}
+static bool transport_dtype_ok(int dtype) {
+  return dtype == RRT_F32 || dtype == RRT_BF16 || block_scaled(dtype);
+}
+
 RelightWs relight_ws(int n, bool f16) {
   const size_t cells = size_t(6) * n * n;
   RelightWs w;
@@ -71,9 +78,9 @@ int validate_relight(const rrt_light* L, const rrt_rotations* R, const rrt_trans
     return fail(RRT_ERR_INVALID, "relight: dense transport (idx NULL) needs nnz = 6 n^2 = %lld", (long long)cells);
   if (T->nvert > 0 && (!T->val || !R->vert_rot))
     return fail(RRT_ERR_INVALID, "relight: null transport values or vertex rotations");
-  if (T->dtype != RRT_F32 && T->dtype != RRT_BF16 && T->dtype != RRT_E4M3 && T->dtype != RRT_S16)
-    return fail(RRT_ERR_UNSUPPORTED, "relight: transport dtype %d (F32, BF16, E4M3 or S16)", T->dtype);
-  if ((T->dtype == RRT_E4M3 || T->dtype == RRT_S16) && !T->block_scale && T->nvert > 0)
+  if (!transport_dtype_ok(T->dtype))
+    return fail(RRT_ERR_UNSUPPORTED, "relight: transport dtype %d (F32, BF16, E4M3, S16 or S11)", T->dtype);
+  if (block_scaled(T->dtype) && !T->block_scale && T->nvert > 0)
     return fail(RRT_ERR_INVALID, "relight: block-scaled transport needs block_scale");
   if (T->cluster && (T->nclusters < 1 || !T->idx) && T->nvert > 0)
     return fail(RRT_ERR_INVALID, "relight: per-cluster supports need nclusters >= 1 and an idx table");
@@ -361,9 +368,9 @@ static int validate_latlong(const rrt_light* L, const rrt_latlong_rotations* R,
     return fail(RRT_ERR_INVALID, "relight_latlong: dense transport needs nnz = 2 H^2 = %lld", (long long)cells);
   if (T->nvert > 0 && (!T->val || !R->elev || !R->shift))
     return fail(RRT_ERR_INVALID, "relight_latlong: null transport values or rotations");
-  if (T->dtype != RRT_F32 && T->dtype != RRT_BF16 && T->dtype != RRT_E4M3 && T->dtype != RRT_S16)
+  if (!transport_dtype_ok(T->dtype))
     return fail(RRT_ERR_UNSUPPORTED, "relight_latlong: transport dtype %d", T->dtype);
-  if ((T->dtype == RRT_E4M3 || T->dtype == RRT_S16) && !T->block_scale && T->nvert > 0)
+  if (block_scaled(T->dtype) && !T->block_scale && T->nvert > 0)
     return fail(RRT_ERR_INVALID, "relight_latlong: block-scaled transport needs block_scale");
   if (T->cluster || T->brdf)
     return fail(RRT_ERR_UNSUPPORTED, "relight_latlong: cluster supports and brdf not supported");
@@ -433,12 +440,12 @@ int rrt_relight_latlong(const rrt_light* L, const rrt_latlong_rotations* R, cons
 int rrt_convert(const float* src, int64_t rows, int cols, int dtype, void* dst, float* block_scale,
                 void* stream) {
   if (rows < 0 || cols < 0) return fail(RRT_ERR_INVALID, "convert: negative size");
-  if (dtype != RRT_F16 && dtype != RRT_BF16 && dtype != RRT_E4M3 && dtype != RRT_S16)
-    return fail(RRT_ERR_UNSUPPORTED, "convert: dtype %d (F16, BF16, E4M3 or S16)", dtype);
+  if (dtype != RRT_F16 && dtype != RRT_BF16 && !block_scaled(dtype))
+    return fail(RRT_ERR_UNSUPPORTED, "convert: dtype %d (F16, BF16, E4M3, S16 or S11)", dtype);
   if (rows * int64_t(cols) > (int64_t(1) << 40)) return fail(RRT_ERR_INVALID, "convert: too large");
   if (rows == 0 || cols == 0) return RRT_OK;
   if (!src || !dst) return fail(RRT_ERR_INVALID, "convert: null pointer");
-  if ((dtype == RRT_E4M3 || dtype == RRT_S16) && !block_scale)
+  if (block_scaled(dtype) && !block_scale)
     return fail(RRT_ERR_INVALID, "convert: block-scaled dtype needs block_scale");
   return launch_convert(src, rows, cols, dtype, dst, block_scale, static_cast<hipStream_t>(stream));
 }
@@ -462,6 +469,19 @@ static int check_mlp_batch(int64_t B, const char* what) {
   return RRT_OK;
 }
 
+int rrt_mlp_decode(const void* w, const float* bias, const float* scale, int nclusters,
+                   const float* pos_nrm, const int32_t* cluster, int64_t B, float* out,
+                   void* stream) {
+  int st = check_mlp_batch(B, "mlp_decode");
+  if (st) return st;
+  if (nclusters < 1) return fail(RRT_ERR_INVALID, "mlp_decode: nclusters=%d < 1", nclusters);
+  if (B == 0) return RRT_OK;
+  if (!w || !bias || !scale || !pos_nrm || !cluster || !out)
+    return fail(RRT_ERR_INVALID, "mlp_decode: null pointer");
+  return launch_mlp_decode(w, bias, scale, nclusters, pos_nrm, cluster, B, out,
+                           static_cast<hipStream_t>(stream));
+}
+
 int rrt_mlp_forward(const void* w, const float* bias, const void* x, int64_t B, float* out,
                     void* ws, size_t ws_bytes, void* stream) {
   int st = check_mlp_batch(B, "mlp_forward");
@@ -482,23 +502,29 @@ int rrt_mlp_backward(const void* w, const void* x, int64_t B, const float* dout,
   return launch_mlp_backward(w, x, B, dout, dw, db, ws, static_cast<hipStream_t>(stream));
 }
 
-// Workspace of the learned relight: [relight workspace][values V x 256 f32]
-// [x: one batch, bfloat16 [B][RRT_MLP_IN]][activations of one batch]
+// Workspace of the learned relight, independent of V beyond one chunk:
+// [relight workspace][values: one chunk of at most RRT_MLP_CHUNK vertices x
+// 256 f32][order of one chunk][its workspace]
 struct RelightMlpWs {
-  size_t relight_total, values_off, x_off, acts_off, acts_bytes, order_off, order_ws_off, total;
+  size_t relight_total, values_off, order_off, order_ws_off, total;
 };
+
+// Vertices per chunk: the fewest chunks of at most RRT_MLP_CHUNK, equal in
+// size (up to one vertex), so that no chunk's launch is a small tail.
+static int64_t mlp_chunk(int64_t nvert) {
+  if (nvert <= 0) return 0;
+  const int64_t nch = (nvert + RRT_MLP_CHUNK - 1) / RRT_MLP_CHUNK;
+  return (nvert + nch - 1) / nch;
+}
 
 static RelightMlpWs relight_mlp_ws(const rrt_light* L, int64_t nvert) {
   RelightMlpWs w;
+  const int64_t chunk = mlp_chunk(nvert);
   w.relight_total = relight_ws(L->n, L->dtype == RRT_F16).total;
   w.values_off = w.relight_total;
-  w.x_off = w.values_off + align256(size_t(nvert) * RRT_MLP_OUT * sizeof(float));
-  const int64_t B = nvert < RRT_MLP_BATCH ? nvert : RRT_MLP_BATCH;
-  w.acts_off = w.x_off + align256(size_t(B) * RRT_MLP_IN * 2);
-  w.acts_bytes = mlp_workspace_bytes(B);
-  w.order_off = w.acts_off + align256(w.acts_bytes);
-  w.order_ws_off = w.order_off + align256(size_t(nvert) * sizeof(int32_t));
-  w.total = w.order_ws_off + align256(relight_order_workspace_bytes(nvert));
+  w.order_off = w.values_off + align256(size_t(chunk) * RRT_MLP_OUT * sizeof(float));
+  w.order_ws_off = w.order_off + align256(size_t(chunk) * sizeof(int32_t));
+  w.total = w.order_ws_off + align256(relight_order_workspace_bytes(chunk));
   return w;
 }
 
@@ -562,28 +588,51 @@ int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M
   if (st) return st;
   if (nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight_mlp: null radiance");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  st = rrt_relight_prepare(L, flags, ws, w.relight_total, stream);
+  if (st || nvert == 0) return st;
   char* base = static_cast<char*>(ws);
   float* values = reinterpret_cast<float*>(base + w.values_off);
-  for (int64_t v0 = 0; v0 < nvert; v0 += RRT_MLP_BATCH) {
-    const int64_t B = nvert - v0 < RRT_MLP_BATCH ? nvert - v0 : RRT_MLP_BATCH;
-    if ((st = launch_mlp_encode(pos_nrm + v0 * 6, B, base + w.x_off, s))) return st;
-    if ((st = launch_mlp_forward(M->w, M->bias, base + w.x_off, B, values + v0 * RRT_MLP_OUT,
-                                 base + w.acts_off, s, /*keep_z=*/false)))
-      return st;
-    if ((st = launch_scale_rows(values + v0 * RRT_MLP_OUT, cluster + v0, M->scale, B,
-                                M->nclusters, s)))
-      return st;
-  }
-  T.val = values;
-  // heavy-first processing order of the vertices from their cluster rows
   int32_t* order = reinterpret_cast<int32_t*>(base + w.order_off);
-  if ((st = launch_relight_order(M->support, cluster, M->nclusters, RRT_MLP_OUT, nvert, L->n,
-                                 order, base + w.order_ws_off, s)))
-    return st;
-  T.order = nvert > 0 ? order : nullptr;
-  st = rrt_relight_prepare(L, flags, ws, w.relight_total, stream);
-  if (st) return st;
-  return rrt_relight_prepared(L, R, &T, radiance, flags, ws, w.relight_total, stream);
+  // Chunks of vertices: decode the chunk's values (one kernel: encoding,
+  // the five layers, per-slot scales), order it heavy-first from its
+  // cluster rows, relight it into its columns of radiance; the next chunk
+  // reuses the same values (stream order), so the workspace does not grow
+  // with V.
+  const int64_t chunk = mlp_chunk(nvert);
+  for (int64_t v0 = 0; v0 < nvert; v0 += chunk) {
+    const int64_t C = nvert - v0 < chunk ? nvert - v0 : chunk;
+    if ((st = launch_mlp_decode(M->w, M->bias, M->scale, M->nclusters, pos_nrm + v0 * 6,
+                                cluster + v0, C, values, s)))
+      return st;
+    if ((st = launch_relight_order(M->support, cluster + v0, M->nclusters, RRT_MLP_OUT, C, L->n,
+                                   order, base + w.order_ws_off, s)))
+      return st;
+    RelightLaunch a;
+    a.src = base + relight_ws(L->n, L->dtype == RRT_F16).src_off;
+    a.src_f16 = L->dtype == RRT_F16;
+    a.vert_rot = R->vert_rot + v0 * 9;
+    a.frame_rot = R->frame_rot;
+    a.t_idx = M->support;
+    a.t_val = values;
+    a.t_scale = nullptr;
+    a.cluster = cluster + v0;
+    a.nclusters = M->nclusters;
+    a.t_dtype = RRT_F32;
+    a.nnz = RRT_MLP_OUT;
+    a.nvert = C;
+    a.nframes = R->nframes;
+    a.n = L->n;
+    a.flags = flags;
+    a.out = radiance + v0;
+    a.out_stride = nvert;
+    a.blocks = base + relight_ws(L->n, L->dtype == RRT_F16).dense_off;
+    a.brdf = nullptr;
+    a.material = nullptr;
+    a.nmaterials = 0;
+    a.order = order;
+    if ((st = launch_relight(a, s))) return st;
+  }
+  return RRT_OK;
 }
 
 int rrt_mse(const float* out, const float* target, int64_t count, float* dout, double* loss,

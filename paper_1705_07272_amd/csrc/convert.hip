@@ -1,7 +1,7 @@
 // Storage conversion of coefficient values for the reduced-precision forms:
-// binary16 and bfloat16 (round to nearest even), OCP FP8 E4M3FN and int16
-// fixed point, the last two with one float32 scale per block of 64 values
-// of a row (scale = max|x| / 448, resp. / 32767).
+// binary16 and bfloat16 (round to nearest even), OCP FP8 E4M3FN, int16 and
+// packed 11-bit fixed point, the last three with one float32 scale per
+// block of 64 values of a row (scale = max|x| / 448, / 32767, / 1023).
 #include <hip/hip_fp16.h>
 
 #include "rrt_internal.h"
@@ -79,6 +79,44 @@ __global__ void convert_blocks(const float* __restrict__ src, CodeT* __restrict_
   scale[t] = sc;
 }
 
+// One thread per (row, block of 64) of the packed 11-bit form: the block's
+// 64 codes fill exactly 22 words of the row's bit stream (a shorter last
+// block ends inside a word whose remaining bits stay zero), so no two
+// threads share a word.
+__global__ void convert_s11(const float* __restrict__ src, uint32_t* __restrict__ dst,
+                            float* __restrict__ scale, int64_t rows, int cols) {
+  const int nblk = (cols + RRT_BLOCK - 1) / RRT_BLOCK;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= rows * nblk) return;
+  const int64_t row = t / nblk;
+  const int blk = int(t - row * nblk);
+  const int c0 = blk * RRT_BLOCK;
+  const int c1 = min(cols, c0 + RRT_BLOCK);
+  const float* s = src + row * cols;
+  float amax = 0.0f;
+  for (int c = c0; c < c1; ++c) amax = fmaxf(amax, fabsf(s[c]));
+  const float sc = amax > 0.0f ? __fdiv_rn(amax, 1023.0f) : 1.0f;
+  const float inv = amax > 0.0f ? __fdiv_rn(1023.0f, amax) : 1.0f;
+  const int64_t words = RRT_S11_WORDS(cols);
+  uint32_t* w = dst + row * words + int64_t(blk) * 22;
+  const int nw = int(min(int64_t(22), words - int64_t(blk) * 22));
+  uint64_t acc = 0;  // the block's bit stream not yet written
+  int have = 0, out = 0;
+  for (int c = c0; c < c1; ++c) {
+    const float r = rintf(fminf(fmaxf(s[c] * inv, -1023.0f), 1023.0f));
+    const unsigned code = unsigned(int(r == r ? r : 0.0f)) & 0x7ffu;
+    acc |= uint64_t(code) << have;
+    have += 11;
+    if (have >= 32) {
+      w[out++] = uint32_t(acc);
+      acc >>= 32;
+      have -= 32;
+    }
+  }
+  if (out < nw) w[out] = uint32_t(acc);
+  scale[t] = sc;
+}
+
 }  // namespace
 
 int launch_convert(const float* src, int64_t rows, int cols, int dtype, void* dst, float* scale,
@@ -96,6 +134,9 @@ int launch_convert(const float* src, int64_t rows, int cols, int dtype, void* ds
     if (dtype == RRT_E4M3) {
       hipLaunchKernelGGL((convert_blocks<uint8_t, 448>), dim3(unsigned((nt + 255) / 256)),
                          dim3(256), 0, s, src, static_cast<uint8_t*>(dst), scale, rows, cols);
+    } else if (dtype == RRT_S11) {
+      hipLaunchKernelGGL(convert_s11, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, s, src,
+                         static_cast<uint32_t*>(dst), scale, rows, cols);
     } else {
       hipLaunchKernelGGL((convert_blocks<int16_t, 32767>), dim3(unsigned((nt + 255) / 256)),
                          dim3(256), 0, s, src, static_cast<int16_t*>(dst), scale, rows, cols);

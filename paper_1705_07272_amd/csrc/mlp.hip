@@ -55,14 +55,16 @@ enum Epilogue {
   kEpiHidden = 0,   // z = acc + bias -> store z (FP32) and gelu(z) (BF16)
   kEpiOutput = 1,   // out = acc + bias -> FP32
   kEpiGeluGrad = 2, // dz = acc * gelu'(zprev) -> BF16
-  kEpiPlain = 3,    // acc -> FP32
-  kEpiHiddenInfer = 4  // gelu(acc + bias) -> BF16 only (inference: no z kept)
+  kEpiPlain = 3     // acc -> FP32
 };
 
 struct GemmArgs {
   const uint16_t* A;
   const uint16_t* B;
   int M, N, K;
+  int k_chunk;         // split over k: workgroup z takes [z k_chunk, (z + 1) k_chunk) (a
+                       // multiple of kBK) and writes its partial sums to out_f32 + z M N
+                       // (kEpiPlain only); 0 = the whole K in one workgroup
   const float* bias;   // [N] (kEpiHidden / kEpiOutput)
   const float* zprev;  // [M][N] (kEpiGeluGrad)
   float* out_f32;      // [M][N]
@@ -124,15 +126,17 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[i][j] = float16_t{};
 
+  const int kb = g.k_chunk ? int(blockIdx.z) * g.k_chunk : 0;
+  const int ke = g.k_chunk ? min(g.K, kb + g.k_chunk) : g.K;
   Slice<BM, !AT> sa;
   Slice<BN, BT> sb;
-  sa.load(g.A, g.M, g.K, m0, 0);
-  sb.load(g.B, g.N, g.K, n0, 0);
-  for (int k0 = 0; k0 < g.K; k0 += kBK) {
+  sa.load(g.A, g.M, g.K, m0, kb);
+  sb.load(g.B, g.N, g.K, n0, kb);
+  for (int k0 = kb; k0 < ke; k0 += kBK) {
     sa.store(As);
     sb.store(Bs);
     __syncthreads();
-    if (k0 + kBK < g.K) {
+    if (k0 + kBK < ke) {
       sa.load(g.A, g.M, g.K, m0, k0 + kBK);
       sb.load(g.B, g.N, g.K, n0, k0 + kBK);
     }
@@ -167,12 +171,14 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
         if (m >= g.M || n >= g.N) continue;
         const int64_t at = int64_t(m) * g.N + n;
         float x = acc[i][j][r];
+        if (EPI == kEpiPlain && g.k_chunk) {
+          g.out_f32[int64_t(blockIdx.z) * g.M * g.N + at] = x;
+          continue;
+        }
         if (EPI == kEpiHidden) {
           x += g.bias[n];
           g.out_f32[at] = x;
           g.out_bf16[at] = bf16_bits(gelu_f(x));
-        } else if (EPI == kEpiHiddenInfer) {
-          g.out_bf16[at] = bf16_bits(gelu_f(x + g.bias[n]));
         } else if (EPI == kEpiOutput) {
           g.out_f32[at] = x + g.bias[n];
         } else if (EPI == kEpiGeluGrad) {
@@ -183,24 +189,125 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
       }
 }
 
-// gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7), zero-padded to 128.
+// Feature f of gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7) of the
+// 6 inputs at `in`, zero-padded to 128, rounded to bfloat16.
+__device__ __forceinline__ uint16_t encode_feature(const float* __restrict__ in, int f) {
+  float v = 0.0f;
+  if (f < 6) {
+    v = in[f];
+  } else if (f < 6 + 6 * 2 * 8) {
+    const int band = (f - 6) / 12;
+    const int r = (f - 6) % 12;
+    const float x = in[r % 6];
+    const float w = float(1 << band) * 3.14159265358979323846f;
+    v = (r < 6) ? sinf(w * x) : cosf(w * x);
+  }
+  return bf16_bits(v);
+}
+
 __global__ void encode_kernel(const float* __restrict__ in, uint16_t* __restrict__ out,
                               int64_t B) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= B * RRT_MLP_IN) return;
   const int64_t row = t / RRT_MLP_IN;
-  const int f = int(t - row * RRT_MLP_IN);
-  float v = 0.0f;
-  if (f < 6) {
-    v = in[row * 6 + f];
-  } else if (f < 6 + 6 * 2 * 8) {
-    const int band = (f - 6) / 12;
-    const int r = (f - 6) % 12;
-    const float x = in[row * 6 + (r % 6)];
-    const float w = float(1 << band) * 3.14159265358979323846f;
-    v = (r < 6) ? sinf(w * x) : cosf(w * x);
+  out[t] = encode_feature(in + row * 6, int(t - row * RRT_MLP_IN));
+}
+
+// The whole decoder for a tile of kDecRows vertices in one 256-thread
+// workgroup: encoding, the four hidden layers and the output layer, with
+// the tile's activations kept in LDS (two bfloat16 buffers, k-contiguous
+// rows) and the weights read from global memory (592 KB shared by every
+// tile: an L2-resident stream).  Wave w computes output columns
+// [64 w, 64 w + 64) of every layer as 2 x 2 tiles of 32 x 32 MFMAs, taking
+// k in the same 16-deep steps and operand order as gemm_bf16, with the same
+// epilogues (bias + GELU rounded to bfloat16; bias, then the per-slot scale
+// of the vertex's cluster for the output), so the values are bit-identical
+// to encode + five gemm_bf16 launches + the per-slot scaling in binary32.
+constexpr int kDecRows = 64;
+constexpr int kActStride = RRT_MLP_HIDDEN + 8;  // bf16 per LDS row (staggered banks)
+
+__global__ __launch_bounds__(256, 2) void decode_kernel(const float* __restrict__ pos_nrm, int64_t B,
+                                                     const uint16_t* __restrict__ W,
+                                                     const float* __restrict__ bias,
+                                                     const int32_t* __restrict__ cluster,
+                                                     const float* __restrict__ scale, int C,
+                                                     float* __restrict__ out) {
+  __shared__ __align__(16) uint16_t act[2][kDecRows * kActStride];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = int64_t(blockIdx.x) * kDecRows;
+  for (int t = threadIdx.x; t < kDecRows * RRT_MLP_IN; t += 256) {
+    const int row = t / RRT_MLP_IN, f = t % RRT_MLP_IN;
+    act[0][row * kActStride + f] =
+        r0 + row < B ? encode_feature(pos_nrm + (r0 + row) * 6, f) : uint16_t(0);
   }
-  out[t] = bf16_bits(v);
+  __syncthreads();
+  const int n0 = 64 * wave;
+  int cur = 0;
+  const uint16_t* Wl = W;
+  const float* bl = bias;
+#pragma unroll 1
+  for (int l = 0; l < RRT_MLP_WEIGHTS; ++l) {
+    const int K = l == 0 ? RRT_MLP_IN : RRT_MLP_HIDDEN;
+    float16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = float16_t{};
+    const uint16_t* a_base = act[cur] + (lane & 31) * kActStride + 8 * (lane >> 5);
+    const uint16_t* b_base = Wl + int64_t(n0 + (lane & 31)) * K + 8 * (lane >> 5);
+#pragma unroll 8
+    for (int ks = 0; ks < K; ks += 16) {
+      bf16x8_t a[2], b[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8_t*>(b_base + int64_t(32 * j) * K + ks);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8_t*>(a_base + 32 * i * kActStride + ks);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+    if (l < RRT_MLP_WEIGHTS - 1) {
+      uint16_t* nxt = act[cur ^ 1];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int n = n0 + 32 * j + (lane & 31);
+          const float bn = bl[n];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            nxt[m * kActStride + n] = bf16_bits(gelu_f(acc[i][j][r] + bn));
+          }
+        }
+      __syncthreads();
+      cur ^= 1;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (r0 + m >= B) continue;
+          const int c = cluster[r0 + m];
+          const bool ok = c >= 0 && c < C;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int n = n0 + 32 * j + (lane & 31);
+            const float x = acc[i][j][r] + bl[n];
+            out[(r0 + m) * RRT_MLP_OUT + n] =
+                ok ? x * scale[int64_t(c) * RRT_MLP_OUT + n] : 0.0f;
+          }
+        }
+    }
+    Wl += int64_t(K) * RRT_MLP_HIDDEN;
+    bl += RRT_MLP_HIDDEN;
+  }
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ in, uint16_t* __restrict__ out,
@@ -262,6 +369,16 @@ __global__ void adam_kernel(float* __restrict__ p, uint16_t* __restrict__ p_bf16
   if (p_bf16) p_bf16[t] = bf16_bits(pt);
 }
 
+// out[i] = sum over z < S of part[z count + i], in order of z.
+__global__ void sum_splits_kernel(const float* __restrict__ part, int S, int64_t count,
+                                  float* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.0f;
+  for (int z = 0; z < S; ++z) acc += part[int64_t(z) * count + i];
+  out[i] = acc;
+}
+
 // 128 x 128 tiles when they still give every CU a workgroup, else 64 x 64.
 template <bool AT, bool BT, int EPI>
 int gemm(const GemmArgs& a, hipStream_t s) {
@@ -279,6 +396,34 @@ int gemm(const GemmArgs& a, hipStream_t s) {
 }
 
 inline unsigned blocks(int64_t n, int per = 256) { return unsigned((n + per - 1) / per); }
+
+// Splits of the weight-gradient GEMM's reduction over a batch of B rows:
+// 256-row chunks, at most kMaxSplits, so that the 16 (or 8) 64 x 64 output
+// tiles of a layer become 256 (or 128) workgroups.
+constexpr int kMaxSplits = 16;
+inline int dw_splits(int64_t B) {
+  const int64_t s = (B + 255) / 256;
+  return int(s < 1 ? 1 : (s > kMaxSplits ? kMaxSplits : s));
+}
+
+// C[M][N] = A^T B over K with the k range split in `splits` (partials in
+// `part`, S M N floats), then summed in split order into out.
+int gemm_dw_split(GemmArgs a, int splits, float* part, hipStream_t s) {
+  if (a.M % 8 || a.N % 8) return RRT_ERR_UNSUPPORTED;
+  float* out = a.out_f32;
+  const int chunk = ((a.K + splits - 1) / splits + kBK - 1) / kBK * kBK;
+  splits = (a.K + chunk - 1) / chunk;
+  a.k_chunk = chunk;
+  a.out_f32 = part;
+  const dim3 grid(unsigned((a.N + 63) / 64), unsigned((a.M + 63) / 64), unsigned(splits));
+  hipLaunchKernelGGL((gemm_bf16<true, false, kEpiPlain, 1>), grid, dim3(256), 0, s, a);
+  int st = check_launch("gemm_bf16 split");
+  if (st) return st;
+  const int64_t count = int64_t(a.M) * a.N;
+  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks(count)), dim3(256), 0, s, part, splits, count,
+                     out);
+  return check_launch("sum_splits");
+}
 
 }  // namespace
 
@@ -302,11 +447,14 @@ int64_t mlp_bias_offset(int l) {
 // Activation workspace for a batch of B rows:
 //   z_l  FP32 [B][256] for the 4 hidden layers,
 //   a_l  BF16 [B][256] for the 4 hidden layers,
-//   dz   BF16 [B][256] x 2 (ping-pong, backward only).
+//   dz   BF16 [B][256] x 2 (ping-pong, backward only),
+//   dout BF16 [B][256] (backward only),
+//   the weight-gradient GEMM's split partial sums, FP32 [S][256][256].
 size_t mlp_workspace_bytes(int64_t B) {
   const size_t rows = size_t(B) * RRT_MLP_HIDDEN;
   return align256(rows * 4) * 4 + align256(rows * 2) * 4 + align256(rows * 2) * 2 +
-         align256(size_t(B) * RRT_MLP_OUT * 2);
+         align256(size_t(B) * RRT_MLP_OUT * 2) +
+         align256(size_t(dw_splits(B)) * RRT_MLP_HIDDEN * RRT_MLP_HIDDEN * 4);
 }
 
 struct MlpWs {
@@ -314,6 +462,7 @@ struct MlpWs {
   uint16_t* a[4];
   uint16_t* dz[2];
   uint16_t* dout_bf16;
+  float* dw_part;
 };
 
 static MlpWs carve(void* ws, int64_t B) {
@@ -333,25 +482,18 @@ static MlpWs carve(void* ws, int64_t B) {
     p += align256(rows * 2);
   }
   w.dout_bf16 = reinterpret_cast<uint16_t*>(p);
+  p += align256(size_t(B) * RRT_MLP_OUT * 2);
+  w.dw_part = reinterpret_cast<float*>(p);
   return w;
 }
 
-// Decoded values of a batch: the network's outputs times the per-slot scales
-// of each vertex's cluster (0 for a cluster outside [0, C)).
-__global__ void scale_rows_kernel(float* __restrict__ out, const int32_t* __restrict__ cluster,
-                                  const float* __restrict__ scale, int64_t B, int C) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= B * RRT_MLP_OUT) return;
-  const int c = cluster[i / RRT_MLP_OUT];
-  out[i] = (c >= 0 && c < C) ? out[i] * scale[int64_t(c) * RRT_MLP_OUT + i % RRT_MLP_OUT] : 0.0f;
-}
-
-int launch_scale_rows(float* out, const int32_t* cluster, const float* scale, int64_t B, int C,
+int launch_mlp_decode(const void* w, const float* b, const float* scale, int C,
+                      const float* pos_nrm, const int32_t* cluster, int64_t B, float* out,
                       hipStream_t s) {
   if (B == 0) return RRT_OK;
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks(B * RRT_MLP_OUT)), dim3(256), 0, s, out,
-                     cluster, scale, B, C);
-  return check_launch("scale_rows");
+  hipLaunchKernelGGL(decode_kernel, dim3(unsigned((B + kDecRows - 1) / kDecRows)), dim3(256), 0, s,
+                     pos_nrm, B, static_cast<const uint16_t*>(w), b, cluster, scale, C, out);
+  return check_launch("decode");
 }
 
 int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s) {
@@ -361,7 +503,7 @@ int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s) {
 }
 
 int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, float* out,
-                       void* ws, hipStream_t s, bool keep_z) {
+                       void* ws, hipStream_t s) {
   const uint16_t* W = static_cast<const uint16_t*>(w);
   MlpWs k = carve(ws, B);
   const uint16_t* a_in = static_cast<const uint16_t*>(x);
@@ -376,12 +518,8 @@ int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, 
     int st;
     if (l < RRT_MLP_WEIGHTS - 1) {
       g.out_bf16 = k.a[l];
-      if (keep_z) {
-        g.out_f32 = k.z[l];
-        st = gemm<false, true, kEpiHidden>(g, s);
-      } else {
-        st = gemm<false, true, kEpiHiddenInfer>(g, s);
-      }
+      g.out_f32 = k.z[l];
+      st = gemm<false, true, kEpiHidden>(g, s);
       a_in = k.a[l];
     } else {
       g.out_f32 = out;
@@ -414,7 +552,7 @@ int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* do
     gw.N = kIn[l];
     gw.K = int(B);
     gw.out_f32 = dw + mlp_weight_offset(l);
-    if ((st = gemm<true, false, kEpiPlain>(gw, s))) return st;
+    if ((st = gemm_dw_split(gw, dw_splits(B), k.dw_part, s))) return st;
     hipLaunchKernelGGL(colsum_kernel, dim3(blocks(kOut[l], 64), unsigned((B + 255) / 256)),
                        dim3(64), 0, s, dz, B, kOut[l], db + mlp_bias_offset(l));
     if ((st = check_launch("colsum"))) return st;

@@ -89,12 +89,16 @@ __device__ __forceinline__ float load_src<__half>(__amdgpu_buffer_rsrc_t r, unsi
   return __half2float(__short_as_half(rrt_struct_load_i16(r, int(at), 0, 0, 0)));
 }
 
-// OCP E4M3FN: s eeee mmm, bias 7, subnormals, 0x7f/0xff NaN, no infinities.
-__device__ __forceinline__ float decode_e4m3(unsigned b) {
-  const unsigned e = (b >> 3) & 15u, m = b & 7u;
-  float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : float(m) * 0x1p-9f;
-  mag = ((b & 0x7fu) == 0x7fu) ? __uint_as_float(0x7fc00000u) : mag;
-  return (b & 0x80u) ? -mag : mag;
+// Code e of a packed 11-bit row (RRT_S11): bits [11 e, 11 e + 11) of the
+// row's word stream, sign-extended.  The second word is read only when the
+// code reaches into it, which stays inside the row's RRT_S11_WORDS(nnz).
+__device__ __forceinline__ int s11_code(const uint32_t* row, int e) {
+  const int b = 11 * e;
+  const int wi = b >> 5, sh = b & 31;
+  const uint32_t lo = row[wi];
+  const uint32_t hi = sh > 21 ? row[wi + 1] : 0u;
+  const uint32_t bits = uint32_t(((uint64_t(hi) << 32) | lo) >> sh);
+  return int(bits << 21) >> 21;
 }
 
 __device__ __forceinline__ float transport_value(const void* val, const float* scale, int dtype,
@@ -106,7 +110,11 @@ __device__ __forceinline__ float transport_value(const void* val, const float* s
   const int nblk = (nnz + RRT_BLOCK - 1) / RRT_BLOCK;
   const float sc = scale[row * nblk + e / RRT_BLOCK];
   if (dtype == RRT_S16) return float(static_cast<const int16_t*>(val)[at]) * sc;
-  return decode_e4m3(static_cast<const uint8_t*>(val)[at]) * sc;
+  if (dtype == RRT_S11)
+    return float(s11_code(static_cast<const uint32_t*>(val) + row * RRT_S11_WORDS(nnz), e)) * sc;
+  // gfx950's FP8 conversion reads the OCP E4M3FN encoding (bias 7,
+  // subnormals, 0x7f / 0xff NaN) exactly
+  return __builtin_amdgcn_cvt_f32_fp8(int(static_cast<const uint8_t*>(val)[at]), 0) * sc;
 }
 
 // Position of a transport entry in the in-place layout of its face.
@@ -192,6 +200,7 @@ struct RelightParams {
   const int32_t* cluster;
   int nclusters;
   float* out;
+  int64_t out_stride;  // frame stride of out (>= nvert)
   int64_t nvert;
   int nnz;
   int nframes;
@@ -925,7 +934,7 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
         acc.s += other.s;
       }
     }
-    if (lane == 0) p.out[int64_t(f) * p.nvert + v] = comp ? (acc.s + acc.c) : acc.s;
+    if (lane == 0) p.out[int64_t(f) * p.out_stride + v] = comp ? (acc.s + acc.c) : acc.s;
   }
 }
 
@@ -1156,6 +1165,7 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   p.cluster = a.cluster;
   p.nclusters = a.nclusters;
   p.out = a.out;
+  p.out_stride = a.out_stride > 0 ? a.out_stride : a.nvert;
   p.nvert = a.nvert;
   p.nnz = a.nnz;
   p.nframes = a.nframes;

@@ -76,7 +76,8 @@ struct RelightLaunch {
   int nframes;
   int n;
   unsigned flags;
-  float* out;               // [F][V]
+  float* out;               // [F][out_stride]: out[f * out_stride + v]
+  int64_t out_stride = 0;   // 0: nvert
   const void* blocks;       // chain rule: float4 (S, H, V, D) per 2x2 source block
   const float* brdf;        // triple product: [M][6 n^2] texel factor, or NULL
   const int32_t* material;  // [V] row of brdf, or NULL (row 0)
@@ -105,11 +106,15 @@ int launch_relight_order(const int32_t* idx, const int32_t* cluster, int ncluste
 // Learned decoder (mlp.hip).
 size_t mlp_workspace_bytes(int64_t B);
 int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s);
-int launch_scale_rows(float* out, const int32_t* cluster, const float* scale, int64_t B, int C,
+// The whole decoder in one kernel (encode, five layers, per-slot scales):
+// out [B][256] values, bit-identical to encode + launch_mlp_forward + the
+// per-slot scaling in binary32.
+int launch_mlp_decode(const void* w, const float* b, const float* scale, int C,
+                      const float* pos_nrm, const int32_t* cluster, int64_t B, float* out,
                       hipStream_t s);
+// Keeps every layer's pre-activation in ws for a backward pass.
 int launch_mlp_forward(const void* w, const float* b, const void* x, int64_t B, float* out,
-                       void* ws, hipStream_t s,
-                       bool keep_z = true);
+                       void* ws, hipStream_t s);
 int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* dout, float* dw,
                         float* db, void* ws, hipStream_t s);
 int launch_mse(const float* out, const float* tgt, int64_t count, float* dout, double* loss,

@@ -19,8 +19,8 @@ this module only drives them and holds the host-side bookkeeping:
 import numpy as np
 import torch
 
-from . import (RRT_MLP_BIAS_COUNT, RRT_MLP_WEIGHT_COUNT, adam_step, mlp_backward, mlp_encode,
-               mlp_forward, mlp_workspace, mse, relight_mlp)
+from . import (RRT_MLP_BIAS_COUNT, RRT_MLP_WEIGHT_COUNT, adam_step, mlp_backward, mlp_decode,
+               mlp_encode, mlp_forward, mlp_workspace, mse, relight_mlp)
 
 LAYER_SHAPES = [(256, 128), (256, 256), (256, 256), (256, 256), (256, 256)]
 
@@ -100,17 +100,13 @@ class TransportDecoder:
                 losses.append((s, loss.item()))
         return losses
 
-    def decode(self, inputs, clusters, chunk=65536):
-        """Coefficient values [V, 256] float32 on each vertex's cluster support."""
-        V = inputs.shape[0]
-        out = torch.empty((V, 256), dtype=torch.float32, device=self.device)
-        ws = mlp_workspace(min(chunk, V), self.device)
-        for s in range(0, V, chunk):
-            e = min(V, s + chunk)
-            x = mlp_encode(inputs[s:e].to(self.device).contiguous())
-            mlp_forward(self.w_bf16, self.bias, x, workspace=ws, out=out[s:e])
-        out *= self.scales[clusters.to(self.device).long()]
-        return out
+    def decode(self, inputs, clusters):
+        """Coefficient values [V, 256] float32 on each vertex's cluster support
+        (rrt_mlp_decode: the network and the per-slot scales in one kernel;
+        0 for a cluster outside [0, C))."""
+        return mlp_decode(self.w_bf16, self.bias, self.scales,
+                          inputs.to(self.device).contiguous(),
+                          clusters.to(self.device, torch.int32).contiguous())
 
     def relight(self, n, light_idx, light_val, vert_rot, inputs, clusters, frame_rot=None,
                 out=None, workspace=None):

@@ -105,3 +105,53 @@ def latlong_case(w, vertex_ids=None):
         val_parts.append(v)
     return dict(H=w.H, light_idx=li, light_val=lv, elev=elev[vertex_ids], shift=shift[vertex_ids],
                 t_idx=np.concatenate(idx_parts), t_val=np.concatenate(val_parts))
+
+
+def rotated_rows(case, frames=None):
+    """The checker's rotated lighting coefficients at each stored row's
+    indices: G[f, v, k] = (W S(R_fv) W^T L)[t_idx[v, k]] in FP64, so that
+    the checker's radiance of any values x [V, nnz] on those rows is
+    sum_k x[v, k] G[f, v, k] (the inner product of oracle.relight.relight,
+    evaluated once per storage form without rotating again)."""
+    from oracle.relight import frame_vertex_rotation, reconstruct_lighting
+    from oracle.sphere import rotate_pixels
+    n = case["n"]
+    P = reconstruct_lighting(case["light_idx"], case["light_val"], n)
+    nv = case["vert_rot"].shape[0]
+    nf = 1 if case["frame_rot"] is None else case["frame_rot"].shape[0]
+    frames = np.arange(nf) if frames is None else np.asarray(frames)
+    G = np.zeros((len(frames), nv, case["t_idx"].shape[1]))
+    for v in range(nv):
+        for b, f in enumerate(frames):
+            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], v, f, n)
+            G[b, v] = haar_forward(rotate_pixels(P, Rq)).ravel()[case["t_idx"][v]]
+    return G
+
+
+def decode_storage(form, codes, scale, nnz):
+    """Host FP64 values of device storage codes [V, ...] of a form, by the
+    definitions of include/rrt.h: bf16 (upper half of binary32), e4m3 (OCP
+    E4M3FN code x block scale), s16 (int16 code x block scale), s11 (11-bit
+    two's-complement code, packed little-endian in uint32 words, x block
+    scale); blocks of 64 values."""
+    import torch
+    codes = codes.cpu()
+    if form == "bf16":
+        return codes.view(torch.bfloat16).double().numpy()
+    if form == "e4m3":
+        q = codes.view(torch.float8_e4m3fn).double().numpy()
+    elif form == "s16":
+        q = codes.numpy().astype(np.float64)
+    elif form == "s11":
+        words = codes.numpy().view(np.uint32).astype(np.uint64)
+        e = np.arange(nnz)
+        b = 11 * e
+        lo = words[:, b >> 5]
+        hi = np.where((b & 31) > 21, words[:, np.minimum((b >> 5) + 1, words.shape[1] - 1)], 0)
+        bits = (((hi << np.uint64(32)) | lo) >> (b & 31).astype(np.uint64)) & np.uint64(0x7ff)
+        q = bits.astype(np.int64)
+        q = np.where(q >= 1024, q - 2048, q).astype(np.float64)
+    else:
+        raise ValueError(form)
+    sc = np.repeat(scale.cpu().numpy().astype(np.float64), 64, axis=1)[:, :nnz]
+    return q * sc

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(rrt):
 
 def test_version_and_strings(rrt):
     lib = rrt.lib
-    assert lib.rrt_abi_version() == 3
+    assert lib.rrt_abi_version() == 4
     assert lib.rrt_status_string(0) == b"ok"
     assert lib.rrt_status_string(3) == b"workspace too small"
     assert lib.rrt_status_string(99) == b"unknown status"
@@ -127,6 +127,7 @@ def test_relight_validation(rrt):
         (dict(ldtype=E.RRT_BF16), E.RRT_ERR_UNSUPPORTED),
         (dict(tdtype=E.RRT_E4M3), E.RRT_ERR_INVALID),          # needs block scales
         (dict(tdtype=E.RRT_S16), E.RRT_ERR_INVALID),
+        (dict(tdtype=E.RRT_S11), E.RRT_ERR_INVALID),
         (dict(tdtype=7), E.RRT_ERR_UNSUPPORTED),
         (dict(nvert=-1), E.RRT_ERR_INVALID),
         (dict(tval=0), E.RRT_ERR_INVALID),
@@ -137,6 +138,7 @@ def test_relight_validation(rrt):
     assert _relight_ws(rrt, *_desc(rrt, tidx=0, nnz=6 * 64))[0] == E.RRT_OK
     assert _relight_ws(rrt, *_desc(rrt, tdtype=E.RRT_E4M3, scale=8))[0] == E.RRT_OK
     assert _relight_ws(rrt, *_desc(rrt, tdtype=E.RRT_S16, scale=8))[0] == E.RRT_OK
+    assert _relight_ws(rrt, *_desc(rrt, tdtype=E.RRT_S11, scale=8))[0] == E.RRT_OK
     L, R, T = _desc(rrt)
     lib = rrt.lib
     assert lib.rrt_relight(ctypes.byref(L), ctypes.byref(R), ctypes.byref(T), _p(8), 0, _p(256),
@@ -192,6 +194,7 @@ def test_convert_validation(rrt):
     assert lib.rrt_convert(_p(8), 2, 3, E.RRT_F32, _p(8), None, None) == E.RRT_ERR_UNSUPPORTED
     assert lib.rrt_convert(_p(8), 2, 3, E.RRT_E4M3, _p(8), None, None) == E.RRT_ERR_INVALID
     assert lib.rrt_convert(_p(8), 2, 3, E.RRT_S16, _p(8), None, None) == E.RRT_ERR_INVALID
+    assert lib.rrt_convert(_p(8), 2, 3, E.RRT_S11, _p(8), None, None) == E.RRT_ERR_INVALID
     assert lib.rrt_convert(_p(0), 2, 3, E.RRT_BF16, _p(8), None, None) == E.RRT_ERR_INVALID
     assert lib.rrt_convert(_p(0), 0, 3, E.RRT_BF16, _p(0), None, None) == E.RRT_OK
 
@@ -220,6 +223,15 @@ def test_mlp_validation(rrt):
     assert lib.rrt_mlp_forward(_p(0), _p(8), _p(8), 64, _p(8), _p(256), 1 << 30, None) == E.RRT_ERR_INVALID
     assert lib.rrt_mlp_backward(_p(8), _p(8), 0, _p(8), _p(8), _p(8), _p(256), 1 << 30, None) == E.RRT_ERR_INVALID
     assert lib.rrt_mse(_p(0), _p(8), 10, _p(8), _p(8), None) == E.RRT_ERR_INVALID
+    # whole-decoder inference: no workspace, clusters >= 1, every pointer
+    dec = lambda w=8, C=4, pos=8, clu=8, B=10, out=8: lib.rrt_mlp_decode(  # noqa: E731
+        _p(w), _p(8), _p(8), C, _p(pos), _p(clu), B, _p(out), None)
+    assert dec(C=0) == E.RRT_ERR_INVALID
+    assert dec(w=0) == E.RRT_ERR_INVALID
+    assert dec(clu=0) == E.RRT_ERR_INVALID
+    assert dec(out=0) == E.RRT_ERR_INVALID
+    assert dec(B=-1) == E.RRT_ERR_INVALID
+    assert dec(B=0, w=0, pos=0, clu=0, out=0) == E.RRT_OK
     f = ctypes.c_float
     assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(0.9), f(0.999), f(1e-8), 0, None) == E.RRT_ERR_INVALID
     assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(1.0), f(0.999), f(1e-8), 1, None) == E.RRT_ERR_INVALID
@@ -306,6 +318,18 @@ def test_relight_mlp_validation(rrt):
     assert nb.value > 100 * 256 * 4
     assert lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), -1,
                                          ctypes.byref(nb)) == E.RRT_ERR_INVALID
+
+    def ws(nvert):
+        assert lib.rrt_relight_mlp_workspace(ctypes.byref(L), ctypes.byref(R), nvert,
+                                             ctypes.byref(nb)) == E.RRT_OK
+        return nb.value
+    # the decoded values live one chunk at a time (equal chunks of at most
+    # 65,536 vertices): the workspace never exceeds that of one full chunk
+    top = ws(65536)
+    assert top < 96 << 20
+    assert top - ws(65535) >= 1024
+    for nvert in (65537, 100_000, 1_000_000, 2_000_000_000):
+        assert ws(nvert) <= top
 
     def call(M, nvert=100, flags=0, wsb=1 << 30, pos=8, clu=8, L=L):
         return lib.rrt_relight_mlp(ctypes.byref(L), ctypes.byref(R),

@@ -3,9 +3,13 @@
 Rounds the FP32 stored transport of the 64-frame 6x128^2 scene to each
 storage form, evaluates the radiance in FP64 with the checker, and compares
 with the FP32-stored reference: this isolates the format's own error from
-any kernel's arithmetic.  Pins the finding that 8-bit-significand BF16
-storage cannot meet 1e-3 on this workload while 16-bit block-scaled fixed
-point stays orders of magnitude below it.
+any kernel's arithmetic.  Measured on this sample (12 vertices x 4 frames,
+max frame rel-L2): BF16 1.40e-3, E4M3 with 64-value block scales 2.15e-2,
+int8 with 64-value block scales 4.3e-3, packed 11-bit fixed point with
+64-value block scales (S11, 1.4375 bytes per value) 4.1e-4, int16 with
+64-value block scales (S16) 9.2e-6.  The 8-bit-significand BF16 and every
+8-bit code miss 1e-3 whatever the kernel does; the 11-bit and 16-bit
+fixed-point forms meet it.
 """
 import numpy as np
 import torch
@@ -22,11 +26,24 @@ def _blocks(x, fn, blk=64):
     return out
 
 
-def _s16(x):
+def _fixed(M):
+    """Block-scaled fixed point with codes in [-M, M] (S16: 32767, S11: 1023,
+    int8: 127): code = RNE(x M / max|x|), value = code max|x| / M."""
+    def f(x):
+        amax = np.abs(x).max(1, keepdims=True).astype(np.float32)
+        amax[amax == 0] = 1
+        inv = np.float32(M) / amax
+        return np.clip(np.rint(x.astype(np.float32) * inv), -M, M) * (amax / np.float32(M))
+    return f
+
+
+def _e4m3(x):
+    """Block-scaled OCP E4M3FN: code = RNE(x 448 / max|x|), value = code max|x| / 448."""
     amax = np.abs(x).max(1, keepdims=True).astype(np.float32)
     amax[amax == 0] = 1
-    inv = np.float32(32767) / amax
-    return np.rint(x.astype(np.float32) * inv) * (amax / np.float32(32767))
+    y = (x.astype(np.float32) * (np.float32(448) / amax)).astype(np.float32)
+    q = torch.from_numpy(y).to(torch.float8_e4m3fn).double().numpy()
+    return q * (amax / np.float32(448))
 
 
 def test_storage_forms_exact_arithmetic():
@@ -37,7 +54,10 @@ def test_storage_forms_exact_arithmetic():
     tv = case["t_val"].astype(np.float64)
     forms = {
         "bf16": torch.from_numpy(case["t_val"]).to(torch.bfloat16).double().numpy(),
-        "s16": _blocks(tv, _s16),
+        "e4m3": _blocks(tv, _e4m3),
+        "int8": _blocks(tv, _fixed(127)),
+        "s11": _blocks(tv, _fixed(1023)),
+        "s16": _blocks(tv, _fixed(32767)),
     }
     frames = [0, 21, 42, 63]
     ref = np.zeros((len(frames), len(vids)))
@@ -50,5 +70,13 @@ def test_storage_forms_exact_arithmetic():
             for k, x in forms.items():
                 got[k][b, a] = x[a] @ g
     err = {k: max(rel_l2(got[k][b], ref[b]) for b in range(len(frames))) for k in forms}
+    print({k: f"{e:.3e}" for k, e in err.items()})
     assert err["bf16"] > 1e-3
+    assert err["e4m3"] > 1e-2
+    assert err["int8"] > 1e-3
+    assert err["s11"] < 6e-4
     assert err["s16"] < 1e-4
+    # each form's error sits near its code's relative step (2^-8 for BF16's
+    # significand, 2^-4 for E4M3, 1/M for the fixed-point codes), so the
+    # ordering is the formats', not the sample's
+    assert err["s16"] < err["s11"] < err["bf16"] < err["int8"] < err["e4m3"]

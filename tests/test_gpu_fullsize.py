@@ -94,59 +94,72 @@ def test_full_cube128_v50000_plain_f32(rrt):
 
 @pytest.fixture(scope="module")
 def frames_case(rrt):
-    from cases import reference
+    from cases import rotated_rows
     w, case, sample, rot, frot, idx, val = _full_case(rrt, 3, 16, 2)
-    case["ref"] = reference(case, return_scale=True)
+    case["G"] = rotated_rows(case)        # [64, 16, 256] FP64
     return w, case, sample, rot, frot, idx, val
 
 
+# Error of each storage form with binary16 lighting and compensated
+# accumulation against the FP64 checker on the FP32 stored inputs (max
+# frame rel-L2 over the 64 frames of the sampled vertices).  The forms'
+# exact-arithmetic floors on the CPU sample of tests/test_forms_cpu.py:
+# S16 9.2e-6, S11 4.1e-4, BF16 1.40e-3, E4M3 2.15e-2 (4.0e-2 on this
+# sample); binary16 lighting adds about 2e-4.  S16 and S11 are held to the
+# 1e-3 target; BF16 and E4M3 cannot meet it and are held to their floors
+# on this sample with a margin.
+FORM_BOUND = {"s16": 1e-3, "s11": 1e-3, "bf16": 2.5e-3, "e4m3": 5e-2}
+
+
 def _frames_run(rrt, frames_case, form):
-    """Returns (max frame rel-L2, max |err| / s) with s = sum_k |T_k ghat_k|."""
-    from cases import frame_errors
+    """Relights the full 50,000-vertex x 64-frame launch with the transport
+    stored in `form`: (1) with FP32 lighting, against the checker fed the
+    decoded stored values (the kernel's own arithmetic, FP32 bar: every
+    element and every frame's rel-L2 <= 1e-5); (2) with binary16 lighting
+    and compensation (the configured form), against the checker on the FP32
+    stored inputs.  Returns the max frame rel-L2 of (2)."""
+    from cases import decode_storage, frame_errors
     w, case, sample, rot, frot, idx, val = frames_case
     scale = None
     if form == "bf16":
         tval = rrt.convert(val, "bf16")
     else:
         tval, scale = rrt.convert(val, form)
-    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
-                      torch.from_numpy(case["light_val"]).cuda().half(),
-                      torch.from_numpy(rot).cuda(), idx, tval, block_scale=scale,
-                      frame_rot=torch.from_numpy(frot).cuda(), compensated=True)
+    sel = torch.from_numpy(sample).cuda().long()
+    dec = decode_storage(form, tval[sel], None if scale is None else scale[sel], w.nnz)
+    G = case["G"]
+    ref_dec = np.einsum("vk,fvk->fv", dec, G)
+    mag_dec = np.einsum("vk,fvk->fv", np.abs(dec), np.abs(G))
+    ref = np.einsum("vk,fvk->fv", case["t_val"].astype(np.float64), G)
+    li = torch.from_numpy(case["light_idx"]).cuda()
+    lv = torch.from_numpy(case["light_val"]).cuda()
+    args = dict(block_scale=scale, frame_rot=torch.from_numpy(frot).cuda())
+    rot_d = torch.from_numpy(rot).cuda()
+    out = rrt.relight(w.n, li, lv, rot_d, idx, tval, **args)
     torch.cuda.synchronize()
-    ref, mag = case["ref"]
+    got = out.cpu().numpy()[:, sample].astype(np.float64)
+    bound = 1e-5 * np.abs(ref_dec) + 2e-7 * mag_dec
+    assert np.all(np.abs(got - ref_dec) <= bound), float(np.max(np.abs(got - ref_dec) / bound))
+    kernel_err = max(frame_errors(got, ref_dec))
+    assert kernel_err <= 1e-5
+    out = rrt.relight(w.n, li, lv.half(), rot_d, idx, tval, compensated=True, **args)
+    torch.cuda.synchronize()
     got = out.cpu().numpy()[:, sample]
-    errs = frame_errors(got, ref)
-    rel_to_mag = float(np.max(np.abs(got - ref) / mag))
-    print(f"cube128 V=50000 F=64 {form} transport + f16 lighting: max frame rel-L2 "
-          f"{max(errs):.3e}, max |err|/sum|T ghat| {rel_to_mag:.3e}")
-    return max(errs), rel_to_mag
+    err = max(frame_errors(got, ref))
+    floor = max(frame_errors(ref_dec, ref))
+    print(f"cube128 V=50000 F=64 {form}: kernel vs checker on the decoded values {kernel_err:.3e}; "
+          f"with f16 lighting vs the FP32-stored checker {err:.3e} (format floor {floor:.3e})")
+    return err
 
 
-def test_full_cube128_v50000_f64frames_s16_f16(rrt, frames_case):
-    """Same scene, 64 frames, block-scaled int16 transport + FP16 lighting,
-    compensated FP32 accumulation: every frame's rel-L2 <= 1e-3 against the
-    FP64 checker on the FP32 stored inputs."""
-    err, _ = _frames_run(rrt, frames_case, "s16")
-    assert err <= 1e-3
-
-
-def test_full_cube128_v50000_f64frames_bf16_f16(rrt, frames_case):
-    """BF16 transport: its 8-bit significand alone costs ~1.6e-3 rel-L2 on
-    this scene even in exact arithmetic (pinned on the CPU by
-    test_storage_forms_exact_arithmetic), so it is judged by the format's
-    element bound: each stored value moves by at most 2^-9 of itself, the
-    binary16 lighting by far less, so |err| <= 2^-8 sum_k |T_k ghat_k|."""
-    _, rel = _frames_run(rrt, frames_case, "bf16")
-    assert rel <= 2.0 ** -8
-
-
-def test_full_cube128_v50000_f64frames_e4m3_f16(rrt, frames_case):
-    """E4M3 transport with 64-value block scales: each normal code is within
-    2^-4 of its value (3-bit significand), subnormal codes within 2^-10 of
-    the block scale: |err| <= (2^-4 + 2^-8) sum_k |T_k ghat_k|."""
-    _, rel = _frames_run(rrt, frames_case, "e4m3")
-    assert rel <= 2.0 ** -4 + 2.0 ** -8
+@pytest.mark.parametrize("form", ["s16", "s11", "bf16", "e4m3"])
+def test_full_cube128_v50000_f64frames_forms(rrt, frames_case, form):
+    """Same scene, 64 frames, each storage form: the kernel matches the
+    checker on its decoded values at the FP32 bar, and the configured form
+    (binary16 lighting, compensated FP32 accumulation) stays within its
+    bound of FORM_BOUND against the FP64 checker on the FP32 stored inputs:
+    1e-3 per frame for S16 and S11 (1.4375 bytes per value)."""
+    assert _frames_run(rrt, frames_case, form) <= FORM_BOUND[form]
 
 
 def test_full_cube128_v50000_triple_product(rrt):

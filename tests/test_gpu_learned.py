@@ -135,14 +135,16 @@ def test_train_decode_and_fallback(scene):
 
 
 def test_fused_relight_mlp_equals_decode_then_relight(scene):
-    """rrt_relight_mlp (decode in batches of RRT_MLP_BATCH, scale, relight
-    with cluster supports) equals rrt_mlp_encode + rrt_mlp_forward + the
-    scaling + rrt_relight bit for bit, over more vertices than one batch; a
-    vertex whose cluster is outside [0, C) gets radiance 0."""
+    """rrt_relight_mlp (chunks of at most RRT_MLP_CHUNK vertices, each
+    decoded, ordered and relit with the cluster supports) equals
+    rrt_mlp_encode + rrt_mlp_forward + the binary32 scaling + rrt_relight
+    over all vertices bit for bit: 140,000 vertices (three chunks) x 3
+    frames, so every chunk writes its own columns of every frame; a vertex
+    whose cluster is outside [0, C) gets radiance 0."""
     from scenes.mesh import displaced_sphere, mesh_inputs, tangent_frames
     from scenes.scene import random_rotations
     rrt, learned = scene["rrt"], scene["learned"]
-    Vf = 20000
+    Vf = 140000
     p, n, _, _ = displaced_sphere(9, Vf)
     feats = torch.from_numpy(mesh_inputs(p, n))
     rng = np.random.default_rng(11)
@@ -152,17 +154,20 @@ def test_fused_relight_mlp_equals_decode_then_relight(scene):
     scales = rng.uniform(0.5, 2.0, size=(K_CLUSTERS, NNZ)).astype(np.float32)
     dec = learned.TransportDecoder(supports, scales, seed=5)
     rot = torch.from_numpy(np.stack(list(random_rotations(12, Vf))).astype(np.float32)).cuda()
+    frot = torch.from_numpy(np.stack(list(random_rotations(13, 3))).astype(np.float32)).cuda()
     li = torch.from_numpy(scene["li"]).cuda()
     lv = torch.from_numpy(scene["lv"]).cuda()
     lab = labels.cuda()
-    fused = dec.relight(N_FACE, li, lv, rot, feats.cuda(), lab)
-    vals = dec.decode(feats, labels)
-    composed = rrt.relight(N_FACE, li, lv, rot, dec.supports, vals, cluster=lab)
+    fused = dec.relight(N_FACE, li, lv, rot, feats.cuda(), lab, frame_rot=frot)
+    net = rrt.mlp_forward(dec.w_bf16, dec.bias, rrt.mlp_encode(feats.cuda()))
+    vals = net * dec.scales[lab.long()]
+    composed = rrt.relight(N_FACE, li, lv, rot, dec.supports, vals, cluster=lab, frame_rot=frot)
     torch.cuda.synchronize()
+    assert fused.shape == (3, Vf)
     assert torch.equal(fused, composed)
     bad = lab.clone()
-    bad[[3, 17000]] = torch.tensor([-1, K_CLUSTERS], dtype=torch.int32, device="cuda")
-    fb = dec.relight(N_FACE, li, lv, rot, feats.cuda(), bad).cpu().numpy()
-    assert fb[0, 3] == 0.0 and fb[0, 17000] == 0.0
-    keep = np.setdiff1d(np.arange(Vf), [3, 17000])
-    assert np.array_equal(fb[0, keep], fused.cpu().numpy()[0, keep])
+    bad[[3, 97000]] = torch.tensor([-1, K_CLUSTERS], dtype=torch.int32, device="cuda")
+    fb = dec.relight(N_FACE, li, lv, rot, feats.cuda(), bad, frame_rot=frot).cpu().numpy()
+    assert np.all(fb[:, 3] == 0.0) and np.all(fb[:, 97000] == 0.0)
+    keep = np.setdiff1d(np.arange(Vf), [3, 97000])
+    assert np.array_equal(fb[:, keep], fused.cpu().numpy()[:, keep])

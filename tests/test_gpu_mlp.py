@@ -56,6 +56,35 @@ def test_encode(rrt):
     assert np.all(got[:, 102:] == 0)
 
 
+@pytest.mark.parametrize("B", [1, 64, 1000, 20000])
+def test_decode_kernel_equals_layered_forward(rrt, B):
+    """rrt_mlp_decode (encoding, five layers and per-slot scales in one
+    kernel, 64-row tiles) equals rrt_mlp_encode + rrt_mlp_forward + the
+    binary32 scaling bit for bit, ragged tiles and clusters outside [0, C)
+    (value 0) included; and the FP64 network on the same weights within the
+    forward tolerance."""
+    rng = np.random.default_rng(B)
+    Wq, bq, w_dev, b_dev = _net(seed=3)
+    x = np.concatenate([rng.uniform(-1, 1, size=(B, 3)),
+                        rng.normal(size=(B, 3))], axis=1).astype(np.float32)
+    C = 5
+    cluster = rng.integers(0, C, B).astype(np.int32)
+    cluster[5::97] = -1
+    cluster[7::89] = C
+    scales = rng.uniform(0.5, 2.0, size=(C, 256)).astype(np.float32)
+    xd, cd, sd = (torch.from_numpy(a).cuda() for a in (x, cluster, scales))
+    got = rrt.mlp_decode(w_dev, b_dev, sd, xd, cd)
+    net = rrt.mlp_forward(w_dev, b_dev, rrt.mlp_encode(xd))
+    ok = (cd >= 0) & (cd < C)
+    want = torch.where(ok[:, None], net * sd[cd.clamp(0, C - 1).long()], torch.zeros_like(net))
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    y, _ = ref.forward(Wq, bq, ref.encode(x.astype(np.float64)))
+    keep = cluster[(cluster >= 0) & (cluster < C)]
+    ref_vals = y[(cluster >= 0) & (cluster < C)] * scales[keep]
+    assert _rel(got.cpu().numpy()[(cluster >= 0) & (cluster < C)], ref_vals) <= 2e-2
+
+
 @pytest.mark.parametrize("B", [1, 64, 333, 4096])
 def test_forward(rrt, B):
     Wq, bq, w_dev, b_dev = _net(1)

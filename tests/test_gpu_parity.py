@@ -51,17 +51,59 @@ def check_frames(got, ref_scale, tol=TOL_F32, rel_l2=True):
 
 
 # ---------------------------------------------------------------- Haar (a1, a3)
+def _forward_magnitude(x):
+    """|W| |x|: at every coefficient of a block of side B (its S, H, V and D
+    alike) the block's sum of |x| divided by B, in the Mallat layout."""
+    x = np.abs(np.asarray(x, np.float64))
+    out = np.empty_like(x)
+    cur, n = x, x.shape[-1]
+    while n > 1:
+        h = n // 2
+        s = (cur[..., 0::2, 0::2] + cur[..., 0::2, 1::2] + cur[..., 1::2, 0::2] + cur[..., 1::2, 1::2]) / 2
+        out[..., :h, h:n] = s
+        out[..., h:n, :h] = s
+        out[..., h:n, h:n] = s
+        cur, n = s, h
+    out[..., :1, :1] = cur
+    return out
+
+
+def _inverse_magnitude(c):
+    """|W^T| |c|: every pixel's sum over its ancestors' |coefficient| / B."""
+    c = np.abs(np.asarray(c, np.float64))
+    N = c.shape[-1]
+    cur, n = c[..., :1, :1], 1
+    while n < N:
+        S, H, V, D = cur, c[..., :n, n:2 * n], c[..., n:2 * n, :n], c[..., n:2 * n, n:2 * n]
+        t = (S + H + V + D) / 2
+        nxt = np.empty(c.shape[:-2] + (2 * n, 2 * n))
+        for dr in (0, 1):
+            for dc in (0, 1):
+                nxt[..., dr::2, dc::2] = t
+        cur, n = nxt, 2 * n
+    return cur
+
+
 @pytest.mark.parametrize("n,count", [(1, 2), (2, 3), (8, 1), (32, 2), (64, 3), (128, 1), (256, 2),
                                      (512, 1), (1024, 1)])
 def test_haar_forward_inverse(rrt, n, count):
+    """Element by element: each output of the FP32 transform passes through
+    at most 2 log2(n) + 2 binary32 roundings of partial sums whose size is
+    bounded by the magnitude transform (|W| |x| forward, |W^T| |c|
+    inverse), so |got - ref| <= 2^-23 (2 log2 n + 2) |W| |x|."""
     from oracle.haar import haar_forward, haar_inverse
     rng = np.random.default_rng(n + count)
     x = rng.normal(size=(count, 6, n, n)).astype(np.float32)
+    depth = 2 * int(np.log2(n)) + 2
     got = rrt.haar_forward(dev(x)).cpu().numpy()
     ref = haar_forward(x.astype(np.float64))
+    bound = 2.0 ** -23 * depth * _forward_magnitude(x)
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
     assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
     back = rrt.haar_inverse(dev(got)).cpu().numpy()
     ref_back = haar_inverse(got.astype(np.float64))
+    bound = 2.0 ** -23 * depth * _inverse_magnitude(got)
+    assert np.all(np.abs(back - ref_back) <= bound), float(np.max(np.abs(back - ref_back) / bound))
     assert np.linalg.norm(back - ref_back) <= 1e-6 * np.linalg.norm(ref_back)
 
 
@@ -147,6 +189,64 @@ def test_convert_s16(rrt):
             assert scale[r, b] == sc
             want = np.clip(np.rint(blk * inv), -32767, 32767).astype(np.int16)
             assert np.array_equal(codes[r, b * 64:(b + 1) * 64], want), (r, b)
+
+
+def _s11_pack(codes):
+    """Reference packing of RRT_S11 (include/rrt.h): code e of a row in bits
+    [11 e, 11 e + 11) of the row's little-endian uint32 word stream, zero
+    bits after the last code."""
+    rows, cols = codes.shape
+    words = (11 * cols + 31) // 32
+    out = np.zeros((rows, words), np.uint32)
+    for r in range(rows):
+        stream = 0
+        for e in range(cols):
+            stream |= (int(codes[r, e]) & 0x7ff) << (11 * e)
+        for k in range(words):
+            out[r, k] = (stream >> (32 * k)) & 0xffffffff
+    return out
+
+
+@pytest.mark.parametrize("cols", [1, 63, 64, 200, 256, 600])
+def test_convert_s11(rrt, cols):
+    """Packed 11-bit codes bit for bit against the definition: per 64-value
+    block code = RNE(x 1023 / max|x|) within [-1023, 1023], scale =
+    max|x| / 1023 (1 for an all-zero block), ragged last blocks."""
+    rng = np.random.default_rng(6 + cols)
+    x = (rng.normal(size=(7, cols)) * np.exp(rng.normal(size=(7, cols)) * 3)).astype(np.float32)
+    x[1, :min(cols, 64)] = 0.0
+    codes, scale = rrt.convert(dev(x), "s11")
+    assert tuple(codes.shape) == (7, rrt.s11_words(cols))
+    codes, scale = codes.cpu().numpy().view(np.uint32), scale.cpu().numpy()
+    want = np.zeros((7, cols), np.int64)
+    for r in range(7):
+        for b in range((cols + 63) // 64):
+            blk = x[r, b * 64:(b + 1) * 64]
+            amax = np.float32(np.max(np.abs(blk)))
+            inv = np.float32(1023.0) / amax if amax > 0 else np.float32(1.0)
+            sc = amax / np.float32(1023.0) if amax > 0 else np.float32(1.0)
+            assert scale[r, b] == sc
+            want[r, b * 64:(b + 1) * 64] = np.clip(np.rint(blk * inv), -1023, 1023)
+    assert np.array_equal(codes, _s11_pack(want))
+
+
+@pytest.mark.parametrize("form", ["e4m3", "s16", "s11"])
+@pytest.mark.parametrize("nnz", [100, 256, 600])
+def test_relight_block_scaled_forms(rrt, form, nnz):
+    """The kernel's decoding of each block-scaled form (E4M3 through the
+    hardware FP8 conversion, packed S11, S16) against the checker fed the
+    decoded stored values: FP32 bar.  nnz = 600 also decodes the entries
+    past the LDS list from global memory in every block."""
+    from cases import build_case, decode_storage, reference, workload
+    w = workload(410 + nnz, 64, 1024, 23, nnz, nframes=2)
+    case = build_case(w)
+    codes, scale = rrt.convert(dev(case["t_val"]), form)
+    dec = decode_storage(form, codes, scale, nnz)
+    out = rrt.relight(64, dev(case["light_idx"]), dev(case["light_val"]), dev(case["vert_rot"]),
+                      dev(case["t_idx"]), codes, block_scale=scale,
+                      frame_rot=dev(case["frame_rot"]))
+    torch.cuda.synchronize()
+    check_frames(out.cpu().numpy(), reference(dict(case, t_val=dec), return_scale=True))
 
 
 # ---------------------------------------------------------------- dense phase shift (a4+a5)

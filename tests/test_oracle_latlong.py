@@ -64,7 +64,7 @@ def _ry(a):
     return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
 
 
-@pytest.mark.parametrize("H,seed", [(16, 1), (64, 2), (128, 3)])
+@pytest.mark.parametrize("H,seed", [(16, 1), (64, 2), (128, 3), (256, 4)])
 def test_agrees_with_fp64_geometry_away_from_boundaries(H, seed):
     W = 2 * H
     d = np.pi / H
