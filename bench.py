@@ -293,7 +293,8 @@ def run_learned(args, w):
     p, nrm, u, rho = displaced_sphere(wt.cfg, wt.nverts)
     frames = tangent_frames(nrm)
     feats = mesh_inputs(p, nrm)
-    centres, labels = learned.kmeans(feats, 64, iters=25, seed=1)
+    K = args.clusters
+    centres, labels = learned.kmeans(feats, K, iters=25, seed=1)
 
     def pixels_of(P, FR, U, RHO):
         def pixels(ids):
@@ -303,7 +304,7 @@ def run_learned(args, w):
         return pixels
 
     pixels = pixels_of(p, frames, u, rho)
-    supports, scales = learned.cluster_supports(pixels, labels, 64, w.nnz, sample_per_cluster=256)
+    supports, scales = learned.cluster_supports(pixels, labels, K, w.nnz, sample_per_cluster=256)
     perm = np.random.default_rng(7).permutation(wt.nverts)
     held, train = np.sort(perm[: wt.nverts // 10]), np.sort(perm[wt.nverts // 10:])
     targets = learned.targets_on_supports(pixels, train, labels, supports)
@@ -331,6 +332,8 @@ def run_learned(args, w):
     else:
         unseen = held
     V = w.nverts
+    label = (w.name if w.nverts == wt.nverts else
+             f"cube{w.n}_k{w.k_light}_mesh_v{V}_f{w.nframes}_mlp")
     dev = torch.device("cuda")
     pix = torch.from_numpy(lighting_pixels(w.cfg, w.n)).to(dev)
     rot = torch.from_numpy(frames.astype(np.float32)).to(dev)
@@ -346,6 +349,8 @@ def run_learned(args, w):
     for s in range(0, V, 512):
         idx[s:s + 512], val[s:s + 512] = rrt.project_rows(pixels(np.arange(s, min(V, s + 512)))
                                                           .contiguous(), w.nnz)
+        if s % 131072 == 0:
+            print(f"stored rows {s}/{V}", file=sys.stderr, flush=True)
     print("stored rows ready", file=sys.stderr, flush=True)
 
     # accuracy on unseen vertices: stored rows, support floor, decoder
@@ -372,7 +377,7 @@ def run_learned(args, w):
         pool = start_cpu_pool(workers)
         inputs = (li[0].cpu().numpy(), lv[0].cpu().numpy(), w.n, rot[sel].cpu().numpy(), frot,
                   idx[sel].cpu().numpy(), val[sel].cpu().numpy())
-        base, errs["stored_rows"], ref = cpu_baseline(pool, workers, inputs, r_rows, w.name)
+        base, errs["stored_rows"], ref = cpu_baseline(pool, workers, inputs, r_rows, label)
         pool.close()
         pool.join()
     else:
@@ -457,6 +462,11 @@ def run_learned(args, w):
     texels = int(sup_faces.sum(1)[lab_dev[:chunk].long()].sum().item()) * w.n * w.n * F
     achieved = texels * OPS_PER_TEXEL / (ms_rel * 1e-3) / 1e12
     dec_tflops = flops / (ms_dec * 1e-3) / 1e12
+    row_faces = torch.zeros((V, 7), device=dev)
+    row_faces.scatter_(1, torch.where(idx >= 0, idx.long() // (w.n * w.n),
+                                      torch.full_like(idx.long(), 6)), 1.0)
+    stored_texels = int((row_faces[:, :6] > 0).sum().item()) * w.n * w.n * F
+    sup_texels_all = int(sup_faces.sum(1)[lab_dev.long()].sum().item()) * w.n * w.n * F
     print(json.dumps({
         "metric": "relit vertices/s at rel-L2<=1e-3 vs FP64 oracle: plain FP32 vs BF16+MLP",
         "value": round(V * F / (ms * 1e-3), 1), "unit": "relit vertices/s", "n_gpus": 1,
@@ -464,10 +474,9 @@ def run_learned(args, w):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 decoder weights/activations, f32 accumulate, f32 relight",
         "data": "synthetic",
-        "config": {"workload": w.name if w.nverts == wt.nverts else
-                   f"cube{w.n}_k{w.k_light}_mesh_v{V}_f{F}_mlp",
+        "config": {"workload": label,
                    "cube_face": w.n, "light_coeffs": w.k_light, "vertices": V, "frames": F,
-                   "clusters": 64, "form": "mlp", "train_steps": args.mlp_steps,
+                   "clusters": K, "form": "mlp", "train_steps": args.mlp_steps,
                    "trained_on": wt.name},
         "accuracy": {"rel_l2": float(f"{errs['decoder']:.4g}"), "bar": 1e-3,
                      "meets_bar": bool(errs["decoder"] <= 1e-3),
@@ -479,9 +488,11 @@ def run_learned(args, w):
         "stored_rows_fp32": {"value": round(V * F / (ms_stored * 1e-3), 1),
                              "ms_per_step": round(ms_stored, 4),
                              "relight_ms": round(ms_stored_relight, 4),
+                             "rotated_texels": stored_texels,
                              "bytes": V * w.nnz * 8},
         "learned": {"decoder_bytes": dec.parameter_bytes(),
                     "relight_mlp_ms": round(ms_mlp_call, 4),
+                    "rotated_texels": sup_texels_all,
                     "split_vertices": chunk, "decode_ms": round(ms_dec, 4),
                     "relight_ms": round(ms_rel, 4),
                     "workspace_bytes": fused_ws.numel()},
@@ -530,6 +541,9 @@ def main():
                          "(default: the next lighting is prepared on a second stream)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--mlp-steps", type=int, default=3000)
+    ap.add_argument("--clusters", type=int, default=64,
+                    help="learned form: k-means clusters of the mesh vertices (one shared "
+                         "coefficient support each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")

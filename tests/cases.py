@@ -155,3 +155,32 @@ def decode_storage(form, codes, scale, nnz):
         raise ValueError(form)
     sc = np.repeat(scale.cpu().numpy().astype(np.float64), 64, axis=1)[:, :nnz]
     return q * sc
+
+
+def _rows_and_reference_job(args):
+    w, vids, li, lv, rot, frot = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        idx, val = stored_transport(w, vids)
+        case = dict(n=w.n, light_idx=li, light_val=lv, vert_rot=rot, frame_rot=frot, t_idx=idx,
+                    t_val=val)
+        ref, mag = reference(case, return_scale=True)
+    return idx, val, ref, mag
+
+
+def rows_and_reference(w, vids, li, lv, rot, frot, workers=8):
+    """stored_transport rows of the vertices `vids` and the checker's
+    (radiance, magnitude scale) [F, len(vids)] for them, over `workers`
+    fresh processes (spawned: this process may hold a GPU context)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    vids = np.asarray(vids)
+    chunks = [c for c in np.array_split(np.arange(len(vids)), 4 * workers) if len(c)]
+    jobs = [(w, vids[c], li, lv, rot[c], frot) for c in chunks]
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_rows_and_reference_job, jobs))
+    idx = np.concatenate([p[0] for p in parts])
+    val = np.concatenate([p[1] for p in parts])
+    ref = np.concatenate([p[2] for p in parts], axis=1)
+    mag = np.concatenate([p[3] for p in parts], axis=1)
+    return idx, val, ref, mag

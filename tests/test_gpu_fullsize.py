@@ -78,17 +78,30 @@ def _full_case(rrt, cfg, sample_count, seed):
 
 
 def test_full_cube128_v50000_plain_f32(rrt):
-    """6x128^2, top-1024 lighting, 50,000 vertices, CSR-256 FP32: sampled
-    outputs of the full launch against the checker, rel-L2 <= 1e-5."""
-    from cases import frame_errors, reference
-    w, case, sample, rot, frot, idx, val = _full_case(rrt, 2, 40, 1)
-    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
-                      torch.from_numpy(case["light_val"]).cuda(), torch.from_numpy(rot).cuda(),
-                      idx, val)
+    """6x128^2, top-1024 lighting, 50,000 vertices, CSR-256 FP32: 1,024
+    sampled outputs of the full launch against the checker (rows and
+    radiance made by the checker in worker processes): every element within
+    the FP32 element bound, rel-L2 <= 1e-5."""
+    from cases import frame_errors, rows_and_reference
+    from oracle.relight import lighting_coefficients
+    from scenes.scene import WORKLOADS, lighting_pixels, vertex_rotations
+    w = WORKLOADS[2]
+    li, lv = lighting_coefficients(lighting_pixels(2, w.n), w.k_light)
+    rot = vertex_rotations(w)
+    sample = _sample(w.nverts, 1024, 1)
+    s_idx, s_val, ref, mag = rows_and_reference(w, sample, li, lv, rot[sample], None)
+    idx, val = _device_rows(rrt, w)
+    sel = torch.from_numpy(sample).cuda().long()
+    idx[sel] = torch.from_numpy(s_idx).cuda()
+    val[sel] = torch.from_numpy(s_val).cuda()
+    out = rrt.relight(w.n, torch.from_numpy(li).cuda(), torch.from_numpy(lv).cuda(),
+                      torch.from_numpy(rot).cuda(), idx, val)
     torch.cuda.synchronize()
-    got = out.cpu().numpy()[:, sample]
-    err = max(frame_errors(got, reference(case)))
-    print(f"cube128 V=50000 sampled rel-L2 {err:.3e}")
+    got = out.cpu().numpy()[:, sample].astype(np.float64)
+    bound = 1e-5 * np.abs(ref) + 2e-7 * mag
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
+    err = max(frame_errors(got, ref))
+    print(f"cube128 V=50000, 1,024 sampled vertices: rel-L2 {err:.3e}")
     assert err <= 1e-5
 
 
@@ -282,8 +295,10 @@ def test_full_cube256_v200000_learned_decoder(rrt):
     vertices, 64 clusters, one rrt_relight_mlp launch over every vertex,
     against the checker on sampled vertices: FP64 encoding and forward on
     the same BF16 weights, per-slot scaling, FP64 relight on the cluster
-    supports.  The device keeps BF16 activations between layers (forward
-    within 2e-2 of the FP64 network), so the radiance is held to 3e-2."""
+    supports.  The device rounds the four hidden layers' activations to
+    bfloat16 (2^-9 relative each) where the FP64 network does not; through
+    layers of about unit gain these add up to at most 4 x 2^-9 = 7.8e-3 of
+    the decoded values and of the radiance they weight (measured 2.5e-3)."""
     from oracle import mlp as ref
     from oracle.relight import lighting_coefficients, relight
     from paper_1705_07272_amd import learned
@@ -320,4 +335,4 @@ def test_full_cube256_v200000_learned_decoder(rrt):
     want = relight(li, lv, w.n, frames[sample], None, supports[labels[sample]], vals)
     err = max(frame_errors(out.cpu().numpy()[:, sample], want))
     print(f"cube256 V=200000 learned decoder sampled rel-L2 {err:.3e}")
-    assert err <= 3e-2
+    assert err <= 4 * 2.0 ** -9

@@ -127,7 +127,9 @@ def test_train_decode_and_fallback(scene):
     form = learned.choose_form(err)
     print(f"decoder held-out relit rel-L2 {err:.3e} -> form {form}")
     assert form == ("mlp" if err <= 1e-3 else "stored")
-    assert err < 0.5                                   # a trained decoder, not noise
+    # a trained decoder, not noise: measured 4.9e-2 on this reduced scene
+    # (the held-out error of an untrained network is of order 1)
+    assert err < 0.1
     # what the decoder gains: bytes replacing V rows of (int32 index + bf16 value)
     stored = V * NNZ * (4 + 2)
     print(f"decoder {dec.parameter_bytes()} B vs stored rows {stored} B")
