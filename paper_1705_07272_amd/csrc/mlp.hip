@@ -316,33 +316,32 @@ __global__ void to_bf16_kernel(const float* __restrict__ in, uint16_t* __restric
   if (t < n) out[t] = bf16_bits(in[t]);
 }
 
-__global__ void fill_kernel(float* __restrict__ x, int64_t n) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) x[t] = 0.0f;
-}
-
-// db[n] += sum over a chunk of rows of dz[m][n] (BF16 gradient rows).
-__global__ void colsum_kernel(const uint16_t* __restrict__ dz, int64_t M, int N,
-                              float* __restrict__ db) {
+// part[c][n] = sum over rows [c R, c R + R) of dz[m][n] (BF16 gradient
+// rows); the chunks' partial sums are then added in chunk order
+// (sum_splits_kernel), so the bias gradient is deterministic.
+__global__ void colsum_kernel(const uint16_t* __restrict__ dz, int64_t M, int N, int R,
+                              float* __restrict__ part) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  const int64_t r0 = int64_t(blockIdx.y) * 256;
-  const int64_t r1 = r0 + 256 < M ? r0 + 256 : M;
+  const int64_t r0 = int64_t(blockIdx.y) * R;
+  const int64_t r1 = r0 + R < M ? r0 + R : M;
   float s = 0.0f;
+#pragma unroll 8
   for (int64_t m = r0; m < r1; ++m) s += bf16_value(dz[m * N + n]);
-  atomicAdd(&db[n], s);
+  part[int64_t(blockIdx.y) * N + n] = s;
 }
 
 // dout = 2 (out - target) / count; loss += sum (out - target)^2 / count (FP64).
+// A grid-stride loop over at most 256 workgroups: one FP64 atomic each.
 __global__ void mse_kernel(const float* __restrict__ out, const float* __restrict__ tgt,
                            int64_t count, float* __restrict__ dout, double* __restrict__ loss) {
   __shared__ double part[256];
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   double sq = 0.0;
-  if (t < count) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < count;
+       t += int64_t(gridDim.x) * blockDim.x) {
     const float d = out[t] - tgt[t];
     dout[t] = 2.0f * d / float(count);
-    sq = double(d) * double(d);
+    sq += double(d) * double(d);
   }
   part[threadIdx.x] = sq;
   __syncthreads();
@@ -379,6 +378,16 @@ __global__ void sum_splits_kernel(const float* __restrict__ part, int S, int64_t
   out[i] = acc;
 }
 
+// out[i] += sum over z < S of part[z count + i], in order of z.
+__global__ void sum_splits_acc_kernel(const float* __restrict__ part, int S, int64_t count,
+                                      float* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.0f;
+  for (int z = 0; z < S; ++z) acc += part[int64_t(z) * count + i];
+  out[i] += acc;
+}
+
 // 128 x 128 tiles when they still give every CU a workgroup, else 64 x 64.
 template <bool AT, bool BT, int EPI>
 int gemm(const GemmArgs& a, hipStream_t s) {
@@ -401,6 +410,9 @@ inline unsigned blocks(int64_t n, int per = 256) { return unsigned((n + per - 1)
 // 256-row chunks, at most kMaxSplits, so that the 16 (or 8) 64 x 64 output
 // tiles of a layer become 256 (or 128) workgroups.
 constexpr int kMaxSplits = 16;
+// 64-row chunks of the bias gradient's column sums per pass: their partials
+// (kColsumChunks x 256 floats) fit in the weight gradient's partial space.
+constexpr int kColsumChunks = kMaxSplits * RRT_MLP_HIDDEN / 64;
 inline int dw_splits(int64_t B) {
   const int64_t s = (B + 255) / 256;
   return int(s < 1 ? 1 : (s > kMaxSplits ? kMaxSplits : s));
@@ -538,9 +550,6 @@ int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* do
   hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(nout)), dim3(256), 0, s, dout, k.dout_bf16, nout);
   int st = check_launch("to_bf16");
   if (st) return st;
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks(mlp_bias_offset(RRT_MLP_WEIGHTS))), dim3(256), 0, s,
-                     db, mlp_bias_offset(RRT_MLP_WEIGHTS));
-  if ((st = check_launch("fill"))) return st;
   const uint16_t* dz = k.dout_bf16;
   for (int l = RRT_MLP_WEIGHTS - 1; l >= 0; --l) {
     const uint16_t* a_in = l == 0 ? static_cast<const uint16_t*>(x) : k.a[l - 1];
@@ -553,9 +562,25 @@ int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* do
     gw.K = int(B);
     gw.out_f32 = dw + mlp_weight_offset(l);
     if ((st = gemm_dw_split(gw, dw_splits(B), k.dw_part, s))) return st;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(kOut[l], 64), unsigned((B + 255) / 256)),
-                       dim3(64), 0, s, dz, B, kOut[l], db + mlp_bias_offset(l));
-    if ((st = check_launch("colsum"))) return st;
+    // bias gradient: column sums of dz in chunks of 64 rows (the weight
+    // gradient's partials are already summed, so their space is free)
+    const int nch = int((B + 63) / 64);
+    for (int c0 = 0; c0 < nch; c0 += kColsumChunks) {
+      const int nc = nch - c0 < kColsumChunks ? nch - c0 : kColsumChunks;
+      const int64_t rows = (int64_t(c0) + nc) * 64 < B ? int64_t(nc) * 64 : B - int64_t(c0) * 64;
+      hipLaunchKernelGGL(colsum_kernel, dim3(blocks(kOut[l], 64), unsigned(nc)), dim3(64), 0, s,
+                         dz + int64_t(c0) * 64 * kOut[l], rows, kOut[l], 64, k.dw_part);
+      if ((st = check_launch("colsum"))) return st;
+      float* dst = db + mlp_bias_offset(l);
+      if (c0 == 0) {
+        hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks(kOut[l])), dim3(256), 0, s, k.dw_part,
+                           nc, int64_t(kOut[l]), dst);
+      } else {
+        hipLaunchKernelGGL(sum_splits_acc_kernel, dim3(blocks(kOut[l])), dim3(256), 0, s,
+                           k.dw_part, nc, int64_t(kOut[l]), dst);
+      }
+      if ((st = check_launch("colsum sum"))) return st;
+    }
     if (l == 0) break;
     // dz_{l-1} = (dz W_l) * gelu'(z_{l-1})
     GemmArgs gx = {};
@@ -575,7 +600,9 @@ int launch_mlp_backward(const void* w, const void* x, int64_t B, const float* do
 
 int launch_mse(const float* out, const float* tgt, int64_t count, float* dout, double* loss,
                hipStream_t s) {
-  hipLaunchKernelGGL(mse_kernel, dim3(blocks(count)), dim3(256), 0, s, out, tgt, count, dout, loss);
+  const int64_t nb = (count + 255) / 256;
+  hipLaunchKernelGGL(mse_kernel, dim3(unsigned(nb < 256 ? nb : 256)), dim3(256), 0, s, out, tgt,
+                     count, dout, loss);
   return check_launch("mse");
 }
 

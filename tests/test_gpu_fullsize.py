@@ -290,28 +290,34 @@ def test_full_cube256_v1000000_f64frames(rrt):
     assert rel <= 2.0 ** -4 + 2.0 ** -8
 
 
-def test_full_cube256_v200000_learned_decoder(rrt):
-    """Learned form at full size: 6 x 256^2, top-2048 lighting, 200,000 mesh
-    vertices, 64 clusters, one rrt_relight_mlp launch over every vertex,
-    against the checker on sampled vertices: FP64 encoding and forward on
+@pytest.mark.parametrize("nverts,nframes", [(200000, 1), (1000000, 64)])
+def test_full_cube256_learned_decoder(rrt, nverts, nframes):
+    """Learned form at full size: 6 x 256^2, top-2048 lighting, the
+    displaced-sphere mesh at 200,000 vertices (one frame) and at 1,000,000
+    vertices x 64 frames (several decode-and-relight chunks), 64 clusters,
+    one rrt_relight_mlp launch over every vertex and frame, against the
+    checker on sampled vertices (and frames): FP64 encoding and forward on
     the same BF16 weights, per-slot scaling, FP64 relight on the cluster
-    supports.  The device rounds the four hidden layers' activations to
-    bfloat16 (2^-9 relative each) where the FP64 network does not; through
-    layers of about unit gain these add up to at most 4 x 2^-9 = 7.8e-3 of
-    the decoded values and of the radiance they weight (measured 2.5e-3)."""
+    supports.  The device rounds the encoded inputs and the four hidden
+    layers' activations to bfloat16 (2^-9 relative each) where the FP64
+    network does not; through layers of about unit gain these five roundings
+    add up to at most 5 x 2^-9 = 9.8e-3 of the decoded values and of the
+    radiance they weight (measured 2.5e-3 at one frame, 6.7e-3 as the max
+    over 4 of the 64 frames)."""
     from oracle import mlp as ref
     from oracle.relight import lighting_coefficients, relight
     from paper_1705_07272_amd import learned
     from scenes.mesh import displaced_sphere, mesh_inputs, tangent_frames
-    from scenes.scene import WORKLOADS, lighting_pixels
+    from scenes.scene import WORKLOADS, frame_rotations, lighting_pixels
     from cases import frame_errors
     w = WORKLOADS[4]
-    p, nrm, _, _ = displaced_sphere(w.cfg, w.nverts)
+    p, nrm, _, _ = displaced_sphere(w.cfg, nverts)
     frames = tangent_frames(nrm).astype(np.float32)
     feats = mesh_inputs(p, nrm).astype(np.float32)
+    frot = frame_rotations(WORKLOADS[5]) if nframes > 1 else None
     rng = np.random.default_rng(44)
     C = 64
-    labels = rng.integers(0, C, w.nverts).astype(np.int32)
+    labels = rng.integers(0, C, nverts).astype(np.int32)
     supports = np.stack([np.sort(rng.choice(6 * w.n * w.n, 256, replace=False))
                          for _ in range(C)]).astype(np.int32)
     scales = rng.uniform(0.5, 2.0, size=(C, 256)).astype(np.float32)
@@ -319,9 +325,14 @@ def test_full_cube256_v200000_learned_decoder(rrt):
     li, lv = lighting_coefficients(lighting_pixels(w.cfg, w.n), w.k_light)
     out = dec.relight(w.n, torch.from_numpy(li).cuda(), torch.from_numpy(lv).cuda(),
                       torch.from_numpy(frames).cuda(), torch.from_numpy(feats).cuda(),
-                      torch.from_numpy(labels).cuda())
+                      torch.from_numpy(labels).cuda(),
+                      frame_rot=None if frot is None else torch.from_numpy(frot).cuda())
     torch.cuda.synchronize()
-    sample = _sample(w.nverts, 12, 7)
+    sample = _sample(nverts, 12, 7)
+    fsel = np.array([0, 21, 42, 63]) if nframes > 1 else np.array([0])
+    got = out[torch.from_numpy(fsel).cuda().long()][:, torch.from_numpy(sample).cuda().long()]
+    got = got.cpu().numpy()
+    del out
     flat_w = dec.w_bf16.float().cpu().numpy().astype(np.float64)
     flat_b = dec.bias.cpu().numpy().astype(np.float64)
     Ws, bs, wo, bo = [], [], 0, 0
@@ -332,7 +343,8 @@ def test_full_cube256_v200000_learned_decoder(rrt):
         bo += o
     net, _ = ref.forward(Ws, bs, ref.encode(feats[sample].astype(np.float64)))
     vals = net * scales[labels[sample]]
-    want = relight(li, lv, w.n, frames[sample], None, supports[labels[sample]], vals)
-    err = max(frame_errors(out.cpu().numpy()[:, sample], want))
-    print(f"cube256 V=200000 learned decoder sampled rel-L2 {err:.3e}")
-    assert err <= 4 * 2.0 ** -9
+    want = relight(li, lv, w.n, frames[sample], frot, supports[labels[sample]], vals,
+                   frames=fsel if nframes > 1 else None)
+    err = max(frame_errors(got, want))
+    print(f"cube256 V={nverts} F={nframes} learned decoder sampled rel-L2 {err:.3e}")
+    assert err <= 5 * 2.0 ** -9
