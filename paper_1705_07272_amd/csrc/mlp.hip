@@ -29,11 +29,15 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint16_t bf16_bits(float x) {
-  const unsigned b = __float_as_uint(x);
-  if ((b & 0x7fffffffu) > 0x7f800000u) return uint16_t((b >> 16) | 0x40u);
-  return uint16_t((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+
+// Two values rounded to bfloat16 (nearest, ties to even) by one
+// v_cvt_pk_bf16_f32: a in the low half, b in the high half.
+__device__ __forceinline__ unsigned bf16x2_bits(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((float2_t){a, b}, bf16x2_t));
 }
+__device__ __forceinline__ uint16_t bf16_bits(float x) { return uint16_t(bf16x2_bits(x, 0.0f)); }
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
 // GELU with the tanh approximation, written with the identity
@@ -217,16 +221,24 @@ __global__ void encode_kernel(const float* __restrict__ in, uint16_t* __restrict
 // workgroup: encoding, the four hidden layers and the output layer, with
 // the tile's activations kept in LDS (two bfloat16 buffers, k-contiguous
 // rows) and the weights read from global memory (592 KB shared by every
-// tile: an L2-resident stream).  Wave w computes output columns
-// [64 w, 64 w + 64) of every layer as 2 x 2 tiles of 32 x 32 MFMAs, taking
-// k in the same 16-deep steps and operand order as gemm_bf16, with the same
-// epilogues (bias + GELU rounded to bfloat16; bias, then the per-slot scale
-// of the vertex's cluster for the output), so the values are bit-identical
-// to encode + five gemm_bf16 launches + the per-slot scaling in binary32.
+// tile: an L2-resident stream).  Wave w computes output features
+// [64 w, 64 w + 64) of every layer for the tile's 64 vertices as the
+// transposed product W A^T: 2 x 2 tiles of 32 x 32 MFMAs with the weights
+// as the first operand, so that each lane ends with four consecutive
+// features of one vertex per register group and stores them with one 8-byte
+// LDS write (or one 16-byte global write for the output).  The k steps, the
+// products and their order are those of gemm_bf16 (a product of two
+// operands is the same either way round), and so are the epilogues (bias +
+// GELU rounded to bfloat16; bias, then the per-slot scale of the vertex's
+// cluster for the output): the values are bit-identical to encode + five
+// gemm_bf16 launches + the per-slot scaling in binary32.
 constexpr int kDecRows = 64;
+constexpr int kDecTiles = kDecRows / 32;  // 32-vertex MFMA tiles per workgroup
+constexpr int kDecWaves = 8;                // waves per workgroup
+constexpr int kDecFeat = RRT_MLP_HIDDEN / 32 / kDecWaves;  // 32-feature tiles per wave
 constexpr int kActStride = RRT_MLP_HIDDEN + 8;  // bf16 per LDS row (staggered banks)
 
-__global__ __launch_bounds__(256, 2) void decode_kernel(const float* __restrict__ pos_nrm, int64_t B,
+__global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* __restrict__ pos_nrm, int64_t B,
                                                      const uint16_t* __restrict__ W,
                                                      const float* __restrict__ bias,
                                                      const int32_t* __restrict__ cluster,
@@ -235,75 +247,88 @@ __global__ __launch_bounds__(256, 2) void decode_kernel(const float* __restrict_
   __shared__ __align__(16) uint16_t act[2][kDecRows * kActStride];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = int64_t(blockIdx.x) * kDecRows;
-  for (int t = threadIdx.x; t < kDecRows * RRT_MLP_IN; t += 256) {
+  for (int t = threadIdx.x; t < kDecRows * RRT_MLP_IN; t += 64 * kDecWaves) {
     const int row = t / RRT_MLP_IN, f = t % RRT_MLP_IN;
     act[0][row * kActStride + f] =
         r0 + row < B ? encode_feature(pos_nrm + (r0 + row) * 6, f) : uint16_t(0);
   }
   __syncthreads();
-  const int n0 = 64 * wave;
+  const int n0 = 32 * kDecFeat * wave;
+  // register r of tile (i, j): feature n0 + 32 i + 8 (r / 4) + 4 (lane / 32) + r % 4,
+  // vertex 32 j + lane % 32
+  const int fl = 4 * (lane >> 5), ml = lane & 31;
   int cur = 0;
   const uint16_t* Wl = W;
   const float* bl = bias;
 #pragma unroll 1
   for (int l = 0; l < RRT_MLP_WEIGHTS; ++l) {
     const int K = l == 0 ? RRT_MLP_IN : RRT_MLP_HIDDEN;
-    float16_t acc[2][2];
+    float16_t acc[kDecFeat][kDecTiles];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = float16_t{};
-    const uint16_t* a_base = act[cur] + (lane & 31) * kActStride + 8 * (lane >> 5);
-    const uint16_t* b_base = Wl + int64_t(n0 + (lane & 31)) * K + 8 * (lane >> 5);
+      for (int j = 0; j < kDecTiles; ++j) acc[i][j] = float16_t{};
+    const uint16_t* a_base = act[cur] + ml * kActStride + 8 * (lane >> 5);
+    const uint16_t* w_base = Wl + int64_t(n0 + ml) * K + 8 * (lane >> 5);
 #pragma unroll 8
     for (int ks = 0; ks < K; ks += 16) {
-      bf16x8_t a[2], b[2];
+      bf16x8_t w[kDecFeat], a[kDecTiles];
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x8_t*>(b_base + int64_t(32 * j) * K + ks);
+      for (int i = 0; i < kDecFeat; ++i)
+        w[i] = *reinterpret_cast<const bf16x8_t*>(w_base + int64_t(32 * i) * K + ks);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const bf16x8_t*>(a_base + 32 * i * kActStride + ks);
+      for (int j = 0; j < kDecTiles; ++j)
+        a[j] = *reinterpret_cast<const bf16x8_t*>(a_base + 32 * j * kActStride + ks);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < kDecTiles; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], a[j], acc[i][j], 0, 0, 0);
     }
-    // register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
     if (l < RRT_MLP_WEIGHTS - 1) {
       uint16_t* nxt = act[cur ^ 1];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int n = n0 + 32 * j + (lane & 31);
-          const float bn = bl[n];
+        for (int g = 0; g < 4; ++g) {
+          const int n = n0 + 32 * i + 8 * g + fl;
+          const float4 b4 = *reinterpret_cast<const float4*>(bl + n);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            nxt[m * kActStride + n] = bf16_bits(gelu_f(acc[i][j][r] + bn));
+          for (int j = 0; j < kDecTiles; ++j) {
+            const int m = 32 * j + ml;
+            uint2 v;
+            v.x = bf16x2_bits(gelu_f(acc[i][j][4 * g] + b4.x), gelu_f(acc[i][j][4 * g + 1] + b4.y));
+            v.y = bf16x2_bits(gelu_f(acc[i][j][4 * g + 2] + b4.z),
+                              gelu_f(acc[i][j][4 * g + 3] + b4.w));
+            *reinterpret_cast<uint2*>(nxt + m * kActStride + n) = v;
           }
         }
       __syncthreads();
       cur ^= 1;
     } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < kDecTiles; ++j) {
+        const int m = 32 * j + ml;
+        if (r0 + m >= B) continue;
+        const int c = cluster[r0 + m];
+        const bool ok = c >= 0 && c < C;
+        float* orow = out + (r0 + m) * RRT_MLP_OUT;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          if (r0 + m >= B) continue;
-          const int c = cluster[r0 + m];
-          const bool ok = c >= 0 && c < C;
+        for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int n = n0 + 32 * j + (lane & 31);
-            const float x = acc[i][j][r] + bl[n];
-            out[(r0 + m) * RRT_MLP_OUT + n] =
-                ok ? x * scale[int64_t(c) * RRT_MLP_OUT + n] : 0.0f;
+          for (int g = 0; g < 4; ++g) {
+            const int n = n0 + 32 * i + 8 * g + fl;
+            const float4 b4 = *reinterpret_cast<const float4*>(bl + n);
+            float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (ok) {
+              const float4 s4 = *reinterpret_cast<const float4*>(scale + int64_t(c) * RRT_MLP_OUT + n);
+              o = make_float4((acc[i][j][4 * g] + b4.x) * s4.x, (acc[i][j][4 * g + 1] + b4.y) * s4.y,
+                              (acc[i][j][4 * g + 2] + b4.z) * s4.z,
+                              (acc[i][j][4 * g + 3] + b4.w) * s4.w);
+            }
+            *reinterpret_cast<float4*>(orow + n) = o;
           }
-        }
+      }
     }
     Wl += int64_t(K) * RRT_MLP_HIDDEN;
     bl += RRT_MLP_HIDDEN;
@@ -503,7 +528,8 @@ int launch_mlp_decode(const void* w, const float* b, const float* scale, int C,
                       const float* pos_nrm, const int32_t* cluster, int64_t B, float* out,
                       hipStream_t s) {
   if (B == 0) return RRT_OK;
-  hipLaunchKernelGGL(decode_kernel, dim3(unsigned((B + kDecRows - 1) / kDecRows)), dim3(256), 0, s,
+  hipLaunchKernelGGL(decode_kernel, dim3(unsigned((B + kDecRows - 1) / kDecRows)),
+                     dim3(64 * kDecWaves), 0, s,
                      pos_nrm, B, static_cast<const uint16_t*>(w), b, cluster, scale, C, out);
   return check_launch("decode");
 }
