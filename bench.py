@@ -73,13 +73,29 @@ def kernel_fingerprint():
 # inputs for a bounded vertex sample, timed on the host cores; its result is
 # also the reference of the timed GPU output on that sample.
 # ----------------------------------------------------------------------------
-def _cpu_relight(args):
-    light_idx, light_val, n, rot, frame_rot, idx, val = args
+def _cpu_relight(job):
+    """One chunk of the checker's work: (kind, args) with kind the method the
+    device ran (the exact rotation, the chain rule, a coarse start, the
+    triple product, the lat-long map) and args its oracle function's."""
+    kind, args = job
     from threadpoolctl import threadpool_limits
-
-    from oracle.relight import relight
     with threadpool_limits(limits=1):     # one core per worker process
-        return relight(light_idx, light_val, n, rot, frame_rot, idx, val)
+        if kind == "exact":
+            from oracle.relight import relight
+            return relight(*args)
+        if kind == "chain":
+            from oracle.chain import relight_chain
+            return relight_chain(*args)
+        if kind == "levels":
+            from oracle.levels import relight_from_level
+            return relight_from_level(*args)
+        if kind == "triple":
+            from oracle.triple import relight_triple
+            return relight_triple(*args)
+        if kind == "latlong":
+            from oracle.latlong import relight_latlong
+            return relight_latlong(*args)
+        raise ValueError(kind)
 
 
 def host_cores():
@@ -103,20 +119,29 @@ def start_cpu_pool(workers):
     return pool
 
 
-def cpu_baseline(pool, workers, inputs, got, label):
-    """inputs = (light_idx, light_val, n, vert_rot [S, 3, 3], frame_rot,
-    t_idx [S, nnz], t_val [S, nnz]): host copies of the device's stored
-    lighting and rows of the S sampled vertices, bit for bit (FP32 values).
-    got [F, S]: the timed device radiance of those vertices.  Returns the
-    baseline record, the max frame rel-L2 of got against the checker and the
-    checker's radiance [F, S]."""
+class PerVertex:
+    """An oracle argument with one row per sampled vertex (split with them)."""
+
+    def __init__(self, rows):
+        self.rows = rows
+
+
+def cpu_baseline(pool, workers, inputs, got, label, kind="exact",
+                 method="FP64 pixel rotate + Haar + dense dot"):
+    """inputs: the `kind` oracle's arguments in order, host copies of the
+    device's stored inputs bit for bit (the lighting's top-K and FP32
+    values, the vertices' rotations and FP32 rows), those with one row per
+    sampled vertex wrapped in PerVertex.  got [F, S]: the timed device
+    radiance of the S sampled vertices.  Returns the baseline record, the
+    max frame rel-L2 of got against the checker and the checker's radiance
+    [F, S]."""
     import numpy as np
 
     from oracle.relight import rel_l2
-    li, lv, n, rot, frot, idx, val = inputs
-    S = rot.shape[0]
+    S = got.shape[1]
     chunks = [c for c in np.array_split(np.arange(S), workers * 4) if len(c)]
-    jobs = [(li, lv, n, rot[c], frot, idx[c], val[c]) for c in chunks]
+    jobs = [(kind, tuple(x.rows[c] if isinstance(x, PerVertex) else x for x in inputs))
+            for c in chunks]
     t0 = time.perf_counter()
     ref = np.concatenate(pool.map(_cpu_relight, jobs), axis=1)
     dt = time.perf_counter() - t0
@@ -129,7 +154,7 @@ def cpu_baseline(pool, workers, inputs, got, label):
             "cores": workers, "kind": "oracle",
             "single_core_value": round(len(chunks[0]) * frames / dt1, 3),
             "sample": f"{S} seeded vertices x {frames} frame(s) of {label}, the device's stored "
-                      f"lighting and rows (FP32), FP64 pixel rotate + Haar + dense dot, "
+                      f"lighting and rows (FP32), {method}, "
                       f"{workers} single-threaded processes, {dt:.1f} s wall"}
     return base, err, ref
 
@@ -189,7 +214,7 @@ def device_inputs(w, form, batch=2048, materials=0):
                 brdf=brdf, material=mat)
 
 
-def run_latlong(args):
+def run_latlong(args, pool=None, workers=0):
     """Longitude-latitude map (Sec. V.A): the timed step is the lighting's
     Haar transform and top-k, then rrt_relight_latlong (reconstruction,
     tables, relight of every vertex under its elevation rotation and
@@ -248,6 +273,29 @@ def run_latlong(args):
     ops = LATLONG_OPS_BASE + LATLONG_OPS_PER_LEVEL * int(np.log2(H))
     achieved = texels * ops / (ms_kernel * 1e-3) / 1e12
     hbm = V * w.nnz * 8 + V * 16 + V * 4
+    base = accuracy = None
+    if pool is not None:
+        # the timed output on a vertex sample against the lat-long checker fed
+        # the device's stored lighting and rows
+        vids = accuracy_sample(V, 1, args.cpu_sample)
+        sel = torch.from_numpy(vids).cuda().long()
+        coef = rrt.haar_forward(pix)
+        li, lv = rrt.topk(coef.view(1, -1), w.k_light)
+        inputs = (li[0].cpu().numpy(), lv[0].cpu().numpy(), H,
+                  PerVertex(elev[sel].cpu().numpy()), PerVertex(shift[sel].cpu().numpy()),
+                  PerVertex(idx[sel].cpu().numpy()), PerVertex(val[sel].cpu().numpy()))
+        got = out[sel].cpu().numpy()[None]
+        base, err, _ = cpu_baseline(pool, workers, inputs, got, w.name, "latlong",
+                                    "FP64 lat-long rotation (binary32 source rule) + Haar + "
+                                    "dense dot")
+        pool.close()
+        pool.join()
+        accuracy = {"rel_l2": float(f"{err:.4g}"), "bar": 1e-5, "meets_bar": bool(err <= 1e-5),
+                    "vertices": int(len(vids)), "frames": 1,
+                    "reference": "FP64 lat-long oracle on the device's stored lighting and "
+                                 "FP32 rows, rel-L2 over the sampled vertices"}
+        print(f"accuracy: rel-L2 {err:.3e} on {len(vids)} vertices; {base['sample']}",
+              file=sys.stderr, flush=True)
     print(json.dumps({
         "metric": "relit vertices/s at rel-L2<=1e-3 vs FP64 oracle: plain FP32 vs BF16+MLP",
         "value": round(V / (ms_step * 1e-3), 1), "unit": "relit vertices/s", "n_gpus": 1,
@@ -264,7 +312,8 @@ def run_latlong(args):
                      "ops_per_texel": ops, "hbm_algorithmic_bytes": hbm,
                      "hbm_achieved_gbs": round(hbm / (ms_kernel * 1e-3) / 1e9, 1),
                      "hbm_peak_gbs": PEAK_HBM_GBS},
-        "cpu_baseline": None}), flush=True)
+        "accuracy": accuracy,
+        "cpu_baseline": base}), flush=True)
 
 
 def run_learned(args, w):
@@ -375,8 +424,9 @@ def run_learned(args, w):
     if not args.no_cpu_baseline:
         workers = host_cores()
         pool = start_cpu_pool(workers)
-        inputs = (li[0].cpu().numpy(), lv[0].cpu().numpy(), w.n, rot[sel].cpu().numpy(), frot,
-                  idx[sel].cpu().numpy(), val[sel].cpu().numpy())
+        inputs = (li[0].cpu().numpy(), lv[0].cpu().numpy(), w.n,
+                  PerVertex(rot[sel].cpu().numpy()), frot, PerVertex(idx[sel].cpu().numpy()),
+                  PerVertex(val[sel].cpu().numpy()))
         base, errs["stored_rows"], ref = cpu_baseline(pool, workers, inputs, r_rows, label)
         pool.close()
         pool.join()
@@ -540,7 +590,7 @@ def main():
                     help="one stream: each step's lighting preparation before its relight "
                          "(default: the next lighting is prepared on a second stream)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
-    ap.add_argument("--mlp-steps", type=int, default=3000)
+    ap.add_argument("--mlp-steps", type=int, default=12000)
     ap.add_argument("--clusters", type=int, default=64,
                     help="learned form: k-means clusters of the mesh vertices (one shared "
                          "coefficient support each)")
@@ -561,13 +611,11 @@ def main():
     if args.nnz:
         w = dataclasses.replace(w, nnz=args.nnz)
 
-    # The checker runs on the exact method's outputs (not the chain-rule or
-    # coarse-start approximations, whose errors the oracle tests measure);
+    # The checker of the method the device runs (the exact rotation, the
+    # chain rule, a coarse start, the triple product, the lat-long map);
     # its worker processes start before any device work.
     pool = workers = None
-    exact = not (args.chain_rule or args.start_level or args.triple)
-    if (not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp"
-            and not args.latlong and exact):
+    if not args.no_cpu_baseline and not args.copy_calibration and args.form != "mlp":
         workers = host_cores()
         pool = start_cpu_pool(workers)
 
@@ -589,7 +637,7 @@ def main():
         run_learned(args, WORKLOADS[5] if args.workload == 5 else WORKLOADS[4])
         return
     if args.latlong:
-        run_latlong(args)
+        run_latlong(args, pool, workers)
         return
 
     inp = device_inputs(w, args.form, materials=args.triple)
@@ -597,6 +645,7 @@ def main():
     n, K, V = w.n, w.k_light, w.nverts
     L = args.start_level
     n_rot = n >> L                     # resolution the rotation runs at
+    idx_full = inp["idx"]
     if L:
         # stored transport rows re-indexed once (a storage transformation)
         inp["idx"] = rrt.coarsen_indices(inp["idx"], n, L)
@@ -679,22 +728,34 @@ def main():
     base = accuracy = None
     if pool is not None:
         import numpy as np
-        vids = accuracy_sample(V, F, args.cpu_sample)
+        # the literal tripling-coefficient sum costs about 6x the double product
+        vids = accuracy_sample(V, F, args.cpu_sample // (4 if args.triple else 1))
         sel = torch.from_numpy(vids).cuda().long()
         last = (counter[0] - 1) % slots
-        inputs = (lis[last][0].cpu().numpy(), lvs[last][0].cpu().numpy(), n,
-                  inp["rot"][sel].cpu().numpy(),
+        inputs = [lis[last][0].cpu().numpy(), lvs[last][0].cpu().numpy(), n,
+                  PerVertex(inp["rot"][sel].cpu().numpy()),
                   None if inp["frot"] is None else inp["frot"].cpu().numpy(),
-                  inp["idx"][sel].cpu().numpy(), inp["val32"][sel].cpu().numpy())
+                  PerVertex(idx_full[sel].cpu().numpy()),
+                  PerVertex(inp["val32"][sel].cpu().numpy())]
+        kind, method = "exact", "FP64 pixel rotate + Haar + dense dot"
+        if args.chain_rule:
+            kind, method = "chain", "FP64 chain-rule rotation + Haar + dense dot"
+        elif L:
+            kind, method = "levels", f"FP64 rotation started {L} levels coarser + dense dot"
+            inputs.append(L)
+        elif args.triple:
+            kind, method = "triple", "FP64 rotate + literal tripling-coefficient sum"
+            inputs += [inp["brdf"].cpu().numpy().astype(np.float64),
+                       PerVertex(inp["material"][sel].cpu().numpy())]
         got = out[:, sel].cpu().numpy()
-        base, err, _ = cpu_baseline(pool, workers, inputs, got, w.name)
+        base, err, _ = cpu_baseline(pool, workers, inputs, got, w.name, kind, method)
         pool.close()
         pool.join()
         bar = 1e-5 if args.form == "f32" else 1e-3
         accuracy = {"rel_l2": float(f"{err:.4g}"), "bar": bar, "meets_bar": bool(err <= bar),
                     "vertices": int(len(vids)), "frames": F,
-                    "reference": "FP64 oracle on the device's stored lighting and FP32 rows, "
-                                 "max over frames of the rel-L2 over the sampled vertices"}
+                    "reference": f"{method} on the device's stored lighting and FP32 rows, max "
+                                 "over frames of the rel-L2 over the sampled vertices"}
         print(f"accuracy: rel-L2 {err:.3e} on {len(vids)} vertices x {F} frames "
               f"(bar {bar:g}); {base['sample']}", file=sys.stderr, flush=True)
 

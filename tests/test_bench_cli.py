@@ -37,9 +37,10 @@ def test_cpu_baseline_reports_the_timed_outputs_error():
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import bench
     from cases import build_case, reference, workload
-    case = build_case(workload(61, 8, 40, 12, 32, nframes=2))
-    inputs = (case["light_idx"], case["light_val"], 8, case["vert_rot"], case["frame_rot"],
-              case["t_idx"], case["t_val"])
+    # as many frames as sampled vertices: only the per-vertex arguments split
+    case = build_case(workload(61, 8, 40, 12, 32, nframes=12))
+    inputs = (case["light_idx"], case["light_val"], 8, bench.PerVertex(case["vert_rot"]),
+              case["frame_rot"], bench.PerVertex(case["t_idx"]), bench.PerVertex(case["t_val"]))
     ref = reference(case)
     pool = bench.start_cpu_pool(2)
     try:
