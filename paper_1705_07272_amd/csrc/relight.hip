@@ -220,15 +220,36 @@ struct RelightParams {
   int ll_tab_off;           // lat-long: byte offset of the tables in LDS
 };
 
+// Correctly rounded binary32 square root of x, for x >= 2^-96 (the lat-long
+// rule takes it of q_x^2 + q_z^2 >= (sin t sin f)^2 >= sin^4(pi / 2H), far
+// above that for every supported H).  The hardware
+// square root is within one ulp, so the rounded result is s or one of its two
+// neighbours s-, s+; the nearest is decided by the signs of the residuals
+// x - s- s and x - s+ s, each exact up to its one rounding in the fma.  A
+// midpoint between two floats squared lies at least a quarter of a square
+// ulp away from every product of adjacent floats, and x, a float of twice
+// the exponent, is a multiple of that grid, so a residual <= 0 (> 0) puts
+// the root below (above) the midpoint.
+__device__ __forceinline__ float sqrt_rn(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float lo = __int_as_float(__float_as_int(s) - 1);
+  const float hi = __int_as_float(__float_as_int(s) + 1);
+  float r = s;
+  r = __builtin_fmaf(-lo, s, x) <= 0.0f ? lo : r;
+  r = __builtin_fmaf(-hi, s, x) > 0.0f ? hi : r;
+  return r;
+}
+
 // Source texel of destination texel (row i, column jc + ...) of a
 // longitude-latitude map with H = 2^logh rows and W = 2H columns, for the
 // elevation rotation R_x(b) = (cb, sb) followed by the azimuth shift sa
 // (Sec. V.A: p = (sin t sin f, cos t, sin t cos f), g(p) = f(R p)).  jc is the
 // destination column already shifted by s_c.  Every operation is one
 // binary32 operation in this order (no contraction), so the decision is
-// reproducible: q = R_x p, rho = |q_xz|, row = #{k < H : q_y <= C_k},
-// c = #{k < H : q_z <= C_k rho} (C_k = cos(k pi / H), decreasing, so both
-// counts are binary searches), column = c for q_x >= 0, else W - 1 - c.
+// reproducible: q = R_x p, rho = |q_xz| (correctly rounded),
+// row = #{k < H : q_y <= C_k}, c = #{k < H : q_z <= C_k rho} (C_k =
+// cos(k pi / H), decreasing, so both counts are binary searches), column = c
+// for q_x >= 0, else W - 1 - c.
 // Returns the flat index over the two H x H squares.
 struct LLTab {
   const float* rs;   // [H] sin of row centres
@@ -247,7 +268,7 @@ __device__ __forceinline__ unsigned latlong_source(const LLTab& t, int i, int jc
   const float pz = t.rs[i] * t.cc[jc];
   const float qy = cb * py - sb * pz;
   const float qz = sb * py + cb * pz;
-  const float rho = __fsqrt_rn(px * px + qz * qz);
+  const float rho = sqrt_rn(px * px + qz * qz);
   int row = 0, c = 0;
   for (int step = H >> 1; step >= 1; step >>= 1) {
     row += (qy <= t.bnd[row + step]) ? step : 0;
@@ -271,7 +292,7 @@ __device__ __forceinline__ unsigned latlong_source_h(const LLTab& t, int i, int 
   const float pz = t.rs[i] * t.cc[jc];
   const float qy = cb * py - sb * pz;
   const float qz = sb * py + cb * pz;
-  const float rho = __fsqrt_rn(px * px + qz * qz);
+  const float rho = sqrt_rn(px * px + qz * qz);
   int row = 0, c = 0;
 #pragma unroll
   for (int step = H >> 1; step >= 1; step >>= 1) {

@@ -661,6 +661,47 @@ def test_relight_latlong_gather_exact(rrt, H):
         assert err.max() < 0.05, (e, sh, int((err >= 0.05).sum()), float(err.max()))
 
 
+def test_relight_latlong_scene_ties_exact(rrt):
+    """Source-index exactness on the 128 x 256 scene's own rotations (its
+    first 64 vertices, one call): about one in six has texels whose azimuth
+    decision is an exact binary32 tie, q_z equal to the rounded C_k rho, which
+    only a correctly rounded rho decides as the rule does.  Rows and lighting
+    as in the texel-ID test above."""
+    from oracle.haar import haar_forward
+    from oracle.latlong import grid, rotate
+    from scenes.latlong import LATLONG_WORKLOADS, rotations
+    w = next(x for x in LATLONG_WORKLOADS.values() if x.H == 128)
+    H, W, nrot = w.H, 2 * w.H, 64
+    elev, shift = rotations(w)
+    elev, shift = elev[:nrot], shift[:nrot]
+    # the premise: some of these rotations hold exact ties
+    St, ct, sf, kf, C = grid(H)
+    i, j = np.arange(H)[:, None], np.arange(W)[None, :]
+    px, py, pz = St[i] * sf[j], ct[i] * np.ones_like(sf[j]), St[i] * kf[j]
+    tied = 0
+    for cb, sb in elev:
+        qz = sb * py + cb * pz
+        rho = np.sqrt(px * px + qz * qz)
+        tied += bool(np.any(qz[None] == C[1:, None, None] * rho[None]))
+    assert tied >= 4, tied
+    ids = np.arange(2 * H * H, dtype=np.float64).reshape(2, H, H)
+    light = haar_forward(ids).ravel().astype(np.float32)
+    h = H // 2
+    rr, cc = np.meshgrid(np.arange(h), np.arange(h), indexing="ij")
+    pos = [f * H * H + (rr + dr) * H + (cc + dc) for f in range(2) for dr, dc in [(0, h), (h, 0), (h, h)]]
+    rows = np.concatenate([p_.ravel() for p_ in pos]).astype(np.int32)
+    R = rows.size
+    out = rrt.relight_latlong(H, dev(np.arange(2 * H * H, dtype=np.int32)), dev(light),
+                              dev(np.repeat(elev, R, axis=0)), dev(np.repeat(shift, R, axis=0)),
+                              dev(np.tile(rows, nrot).reshape(-1, 1)),
+                              dev(np.ones((nrot * R, 1), np.float32)))
+    got = out.cpu().numpy().reshape(nrot, R)
+    for v in range(nrot):
+        want = haar_forward(rotate(ids, elev[v, 0], elev[v, 1], shift[v, 0], shift[v, 1])).ravel()[rows]
+        err = np.abs(got[v] - want)
+        assert err.max() < 0.05, (v, elev[v], shift[v], int((err >= 0.05).sum()))
+
+
 def test_relight_latlong_edge_cases(rrt):
     """Empty vertex set; shifts reduced mod 2H; binary16 lighting; out-of-range
     transport entries ignored."""
