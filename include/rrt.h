@@ -60,8 +60,10 @@ extern "C" {
 
 /* 3: rotations quantised at 2^(22 - log2 n) instead of 2^20 (same calls,
    slightly different source texels for general rotations).
-   4: transport dtype RRT_S11 (packed 11-bit block-scaled fixed point). */
-#define RRT_ABI_VERSION 4
+   4: transport dtype RRT_S11 (packed 11-bit block-scaled fixed point).
+   5: rrt_mlp_decode and rrt_relight_mlp take the weights in the decoder
+   layout of rrt_mlp_pack. */
+#define RRT_ABI_VERSION 5
 
 typedef enum {
   RRT_OK = 0,
@@ -358,15 +360,25 @@ int rrt_mlp_workspace(int64_t B, size_t* bytes);
    following rrt_mlp_backward on the same batch. */
 int rrt_mlp_forward(const void* w, const float* bias, const void* x, int64_t B, float* out,
                     void* ws, size_t ws_bytes, void* stream);
+/* Decoder weight layout: w_dec receives the RRT_MLP_WEIGHT_COUNT bfloat16
+   weights w (row-major per layer, as above) reordered for the matrix-core
+   operands of rrt_mlp_decode.  Each layer keeps its offset and size; inside
+   it, the operand of rows 32 t .. 32 t + 31 at inputs 16 s .. 16 s + 15 is
+   the 512 values at (t * K / 16 + s) * 512 (K = the layer's inputs), value
+   8 (m + 32 h) + e holding w[32 t + m][16 s + 8 h + e] (m < 32, h < 2,
+   e < 8), so that a wave reads it as one contiguous 1 KiB.  w and w_dec
+   are 16-byte aligned device buffers that do not overlap. */
+int rrt_mlp_pack(const void* w, void* w_dec, void* stream);
 /* Inference of the whole decoder in one kernel, for the transport values of
    B vertices: values[v][j] = out(encode(pos_nrm[v]))[j] * scale[cluster[v]][j]
-   (0 for a cluster outside [0, nclusters)).  pos_nrm [B][6] float32,
+   (0 for a cluster outside [0, nclusters)).  w_dec: the weights in the
+   decoder layout (rrt_mlp_pack), 16-byte aligned; pos_nrm [B][6] float32,
    cluster [B] int32, scale [nclusters][256] float32, values [B][256]
-   float32.  No workspace: each 256-thread workgroup keeps the activations
+   float32.  No workspace: each 512-thread workgroup keeps the activations
    of 64 vertices in LDS and reads the weights from global memory.  The
-   values are bit-identical to rrt_mlp_encode + rrt_mlp_forward followed
-   by the scaling in binary32. */
-int rrt_mlp_decode(const void* w, const float* bias, const float* scale, int nclusters,
+   values are bit-identical to rrt_mlp_encode + rrt_mlp_forward (row-major
+   weights) followed by the scaling in binary32. */
+int rrt_mlp_decode(const void* w_dec, const float* bias, const float* scale, int nclusters,
                    const float* pos_nrm, const int32_t* cluster, int64_t B, float* values,
                    void* stream);
 /* Gradients of a scalar whose gradient with respect to out is dout [B][256]:
@@ -407,7 +419,7 @@ int rrt_adam_step(float* param, void* param_bf16, float* m, float* v, const floa
  * --------------------------------------------------------------------- */
 #define RRT_MLP_CHUNK 65536
 typedef struct {
-  const void* w;           /* RRT_MLP_WEIGHT_COUNT bfloat16 weights */
+  const void* w;           /* RRT_MLP_WEIGHT_COUNT bfloat16 weights, decoder layout */
   const float* bias;       /* RRT_MLP_BIAS_COUNT float32 biases */
   const int32_t* support;  /* [C][RRT_MLP_OUT] flat coefficient indices */
   const float* scale;      /* [C][RRT_MLP_OUT] per-slot output scales */

@@ -22,7 +22,7 @@ from ._abi import (RRT_BF16, RRT_BLOCK, RRT_CHAIN_RULE, RRT_COMPENSATED, RRT_E4M
 
 __all__ = ["haar_forward", "haar_inverse", "topk", "coarsen_indices", "haar_phase_shift", "relight",
            "relight_noalloc",
-           "relight_latlong", "relight_mlp", "relight_order", "mlp_encode", "mlp_decode",
+           "relight_latlong", "relight_mlp", "relight_order", "mlp_encode", "mlp_pack", "mlp_decode",
            "mlp_forward", "mlp_backward", "mlp_workspace", "mse", "adam_step",
            "relight_workspace_bytes", "PreparedLighting", "prepare_lighting", "convert",
            "project_rows", "RrtError", "lib"]
@@ -405,7 +405,8 @@ def relight_latlong(H, light_idx, light_val, elev, shift, t_idx, t_val, block_sc
 def relight_mlp(n, light_idx, light_val, vert_rot, weights, bias, supports, scales, pos_nrm,
                 cluster, frame_rot=None, compensated=False, out=None, workspace=None):
     """radiance [F, V] float32 with the learned transport (rrt_relight_mlp):
-    weights RRT_MLP_WEIGHT_COUNT bfloat16, bias RRT_MLP_BIAS_COUNT float32,
+    weights RRT_MLP_WEIGHT_COUNT bfloat16 in the decoder layout (mlp_pack),
+    bias RRT_MLP_BIAS_COUNT float32,
     supports [C, 256] int32, scales [C, 256] float32, pos_nrm [V, 6]
     float32, cluster [V] int32."""
     _light_shapes(light_idx, light_val)
@@ -557,11 +558,23 @@ def mlp_encode(pos_nrm):
     return x
 
 
-def mlp_decode(w_bf16, bias, scales, pos_nrm, cluster, out=None):
+def mlp_pack(w_bf16, out=None):
+    """The weights in the decoder layout (rrt_mlp_pack): [294912] bfloat16,
+    what mlp_decode and relight_mlp take."""
+    _numel(w_bf16, "weights", RRT_MLP_WEIGHT_COUNT)
+    _numel(out, "out", RRT_MLP_WEIGHT_COUNT)
+    out = torch.empty(RRT_MLP_WEIGHT_COUNT, dtype=torch.bfloat16, device=w_bf16.device) if out is None else out
+    check(lib.rrt_mlp_pack(_dev(w_bf16, "w", torch.bfloat16), _dev(out, "out", torch.bfloat16),
+                           _stream()))
+    return out
+
+
+def mlp_decode(w_dec, bias, scales, pos_nrm, cluster, out=None):
     """Decoded transport values [B, 256] float32 (rrt_mlp_decode): the whole
     network and the per-slot scales of each vertex's cluster in one kernel.
-    scales [C, 256] float32, pos_nrm [B, 6] float32, cluster [B] int32."""
-    _mlp_shapes(w_bf16, bias)
+    w_dec: the weights in the decoder layout (mlp_pack); scales [C, 256]
+    float32, pos_nrm [B, 6] float32, cluster [B] int32."""
+    _mlp_shapes(w_dec, bias)
     if scales.dim() != 2 or scales.shape[1] != RRT_MLP_OUT:
         raise ValueError(f"scales has shape {tuple(scales.shape)}, expected (C, {RRT_MLP_OUT})")
     if pos_nrm.dim() != 2 or pos_nrm.shape[1] != 6:
@@ -570,7 +583,7 @@ def mlp_decode(w_bf16, bias, scales, pos_nrm, cluster, out=None):
     _numel(cluster, "cluster", B)
     _numel(out, "out", B * RRT_MLP_OUT)
     out = torch.empty((B, RRT_MLP_OUT), dtype=torch.float32, device=pos_nrm.device) if out is None else out
-    check(lib.rrt_mlp_decode(_dev(w_bf16, "w", torch.bfloat16), _dev(bias, "bias", torch.float32),
+    check(lib.rrt_mlp_decode(_dev(w_dec, "w_dec", torch.bfloat16), _dev(bias, "bias", torch.float32),
                              _dev(scales, "scales", torch.float32), scales.shape[0],
                              _dev(pos_nrm, "pos_nrm", torch.float32),
                              _dev(cluster, "cluster", torch.int32), B,

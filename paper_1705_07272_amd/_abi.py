@@ -101,6 +101,7 @@ SIGNATURES = {
                                      c_void_p, c_size_t, c_void_p]),
     "rrt_convert": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "rrt_mlp_encode": (c_int, [c_void_p, c_int64, c_void_p, c_void_p]),
+    "rrt_mlp_pack": (c_int, [c_void_p, c_void_p, c_void_p]),
     "rrt_mlp_workspace": (c_int, [c_int64, P(c_size_t)]),
     "rrt_mlp_decode": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int64,
                                c_void_p, c_void_p]),

@@ -469,6 +469,15 @@ static int check_mlp_batch(int64_t B, const char* what) {
   return RRT_OK;
 }
 
+int rrt_mlp_pack(const void* w, void* w_dec, void* stream) {
+  if (!w || !w_dec) return fail(RRT_ERR_INVALID, "mlp_pack: null pointer");
+  const auto a = reinterpret_cast<uintptr_t>(w), b = reinterpret_cast<uintptr_t>(w_dec);
+  const uintptr_t n = uintptr_t(RRT_MLP_WEIGHT_COUNT) * 2;
+  if (a < b + n && b < a + n) return fail(RRT_ERR_INVALID, "mlp_pack: w and w_dec overlap");
+  if ((a | b) % 16) return fail(RRT_ERR_INVALID, "mlp_pack: w and w_dec must be 16-byte aligned");
+  return launch_mlp_pack(w, w_dec, static_cast<hipStream_t>(stream));
+}
+
 int rrt_mlp_decode(const void* w, const float* bias, const float* scale, int nclusters,
                    const float* pos_nrm, const int32_t* cluster, int64_t B, float* out,
                    void* stream) {
@@ -478,6 +487,7 @@ int rrt_mlp_decode(const void* w, const float* bias, const float* scale, int ncl
   if (B == 0) return RRT_OK;
   if (!w || !bias || !scale || !pos_nrm || !cluster || !out)
     return fail(RRT_ERR_INVALID, "mlp_decode: null pointer");
+  if (reinterpret_cast<uintptr_t>(w) % 16) return fail(RRT_ERR_INVALID, "mlp_decode: weights not 16-byte aligned");
   return launch_mlp_decode(w, bias, scale, nclusters, pos_nrm, cluster, B, out,
                            static_cast<hipStream_t>(stream));
 }
@@ -535,6 +545,8 @@ static int validate_relight_mlp(const rrt_light* L, const rrt_rotations* R, cons
     return fail(RRT_ERR_INVALID, "relight_mlp: nvert=%lld out of range", (long long)nvert);
   if (!M->w || !M->bias || !M->support || !M->scale || M->nclusters < 1)
     return fail(RRT_ERR_INVALID, "relight_mlp: decoder needs weights, biases, supports, scales and nclusters >= 1");
+  if (reinterpret_cast<uintptr_t>(M->w) % 16)
+    return fail(RRT_ERR_INVALID, "relight_mlp: weights not 16-byte aligned");
   T->nvert = nvert;
   T->nnz = RRT_MLP_OUT;
   T->idx = M->support;

@@ -193,28 +193,71 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
       }
 }
 
-// Feature f of gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7) of the
-// 6 inputs at `in`, zero-padded to 128, rounded to bfloat16.
-__device__ __forceinline__ uint16_t encode_feature(const float* __restrict__ in, int f) {
-  float v = 0.0f;
-  if (f < 6) {
-    v = in[f];
-  } else if (f < 6 + 6 * 2 * 8) {
-    const int band = (f - 6) / 12;
-    const int r = (f - 6) % 12;
-    const float x = in[r % 6];
-    const float w = float(1 << band) * 3.14159265358979323846f;
-    v = (r < 6) ? sinf(w * x) : cosf(w * x);
+// Band q of gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7) of the 6
+// inputs at `in`, rounded to bfloat16 into the feature row `row`: the six
+// sines (features 6 + 12 q + i) and cosines (6 + 12 q + 6 + i) of one
+// argument each (one shared range reduction), band 0 also the inputs
+// themselves (features 0..5); band q writes the zero padding of features
+// 102 + 4 q .. 102 + 4 q + 3 below 128.  The six inputs are loaded together.
+constexpr int kEncBands = 8;
+static_assert(6 + 12 * kEncBands + 4 * (kEncBands - 1) >= RRT_MLP_IN, "padding per band");
+
+__device__ __forceinline__ void encode_band(const float* __restrict__ in, int q,
+                                            uint16_t* __restrict__ row) {
+  float x[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) x[i] = in[i];
+  const float w = float(1 << q) * 3.14159265358979323846f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    float sn, cs;
+    sincosf(w * x[i], &sn, &cs);
+    row[6 + 12 * q + i] = bf16_bits(sn);
+    row[6 + 12 * q + 6 + i] = bf16_bits(cs);
   }
-  return bf16_bits(v);
+  if (q == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) row[i] = bf16_bits(x[i]);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int f = 6 + 12 * kEncBands + 4 * q + e;
+    if (f < RRT_MLP_IN) row[f] = 0;
+  }
 }
 
+// One thread per (row, band).
 __global__ void encode_kernel(const float* __restrict__ in, uint16_t* __restrict__ out,
                               int64_t B) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= B * RRT_MLP_IN) return;
-  const int64_t row = t / RRT_MLP_IN;
-  out[t] = encode_feature(in + row * 6, int(t - row * RRT_MLP_IN));
+  if (t >= B * kEncBands) return;
+  const int64_t r = t / kEncBands;
+  encode_band(in + r * 6, int(t - r * kEncBands), out + r * RRT_MLP_IN);
+}
+
+// Decoder weight layout (rrt_mlp_pack): layer l keeps its offset and size
+// of the row-major packing (256 rows of K = 128 or 256 inputs); inside it
+// the MFMA operand of feature tile t (rows 32 t .. 32 t + 31) at k-step s
+// (k = 16 s .. 16 s + 15) is 512 values at (t * K / 16 + s) * 512, lane
+// m + 32 h of the 64 holding W[32 t + m][16 s + 8 h + e], e = 0..7, at
+// 8 (m + 32 h) + e.  One thread per 8-value piece (16-byte copies).
+__global__ void pack_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ out) {
+  int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= RRT_MLP_WEIGHT_COUNT / 8) return;
+  int64_t base = 0;
+  int K = RRT_MLP_IN;
+  for (int l = 0; l < RRT_MLP_WEIGHTS; ++l) {
+    K = l == 0 ? RRT_MLP_IN : RRT_MLP_HIDDEN;
+    const int64_t pieces = int64_t(RRT_MLP_HIDDEN) * K / 8;
+    if (p < pieces) break;
+    p -= pieces;
+    base += int64_t(RRT_MLP_HIDDEN) * K;
+  }
+  const int S = K / 16;
+  const int lane = int(p % 64), s = int((p / 64) % S), t = int(p / 64 / S);
+  const int m = lane & 31, h = lane >> 5;
+  const uint4 v = *reinterpret_cast<const uint4*>(w + base + int64_t(32 * t + m) * K + 16 * s + 8 * h);
+  *reinterpret_cast<uint4*>(out + base + p * 8) = v;
 }
 
 // The whole decoder for a tile of kDecRows vertices in one 256-thread
@@ -238,6 +281,62 @@ constexpr int kDecWaves = 8;                // waves per workgroup
 constexpr int kDecFeat = RRT_MLP_HIDDEN / 32 / kDecWaves;  // 32-feature tiles per wave
 constexpr int kActStride = RRT_MLP_HIDDEN + 8;  // bf16 per LDS row (staggered banks)
 
+// One layer's products for the tile: acc[i][j] = W rows [n0 + 32 i, +32) x
+// the tile's activations of vertices [32 j, +32), over k = 0..K-1 in steps of
+// 16.  The weights come from L2 in the decoder layout (one 16-byte load per
+// lane, feature tile and step: 1 KiB contiguous per wave, eight whole cache
+// lines); they are loaded kDecAhead steps ahead into a register ring, so
+// that that many loads are in flight while the products run instead of
+// each step waiting for its own.  K is a compile-time constant so that the
+// loop and the ring unroll.
+constexpr int kDecAhead = 8;
+
+template <int K>
+__device__ __forceinline__ void decode_products(const uint16_t* __restrict__ act,
+                                                const uint16_t* __restrict__ Wl, int n0, int lane,
+                                                float16_t (&acc)[kDecFeat][kDecTiles]) {
+  constexpr int kSteps = K / 16;
+  constexpr int kAhead = kDecAhead < kSteps ? kDecAhead : kSteps;
+  const int ml = lane & 31;
+#pragma unroll
+  for (int i = 0; i < kDecFeat; ++i)
+#pragma unroll
+    for (int j = 0; j < kDecTiles; ++j) acc[i][j] = float16_t{};
+  const uint16_t* a_base = act + ml * kActStride + 8 * (lane >> 5);
+  // fragment (tile n0 / 32 + i, step s) of this lane: 8 values at
+  // ((tile * kSteps + s) * 64 + lane) * 8 of the layer's decoder layout
+  const uint16_t* w_base = Wl + (int64_t(n0 / 32) * kSteps * 64 + lane) * 8;
+  bf16x8_t ring[kAhead][kDecFeat];
+#pragma unroll
+  for (int s = 0; s < kAhead; ++s)
+#pragma unroll
+    for (int i = 0; i < kDecFeat; ++i)
+      ring[s][i] = *reinterpret_cast<const bf16x8_t*>(w_base + (int64_t(i) * kSteps + s) * 512);
+#pragma unroll
+  for (int s = 0; s < kSteps; ++s) {
+    // keep each step's loads in their step (the scheduler would otherwise
+    // sink them next to their use to save registers)
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8_t w[kDecFeat], a[kDecTiles];
+#pragma unroll
+    for (int i = 0; i < kDecFeat; ++i) w[i] = ring[s % kAhead][i];
+    if (s + kAhead < kSteps) {
+#pragma unroll
+      for (int i = 0; i < kDecFeat; ++i)
+        ring[s % kAhead][i] = *reinterpret_cast<const bf16x8_t*>(
+            w_base + (int64_t(i) * kSteps + s + kAhead) * 512);
+    }
+#pragma unroll
+    for (int j = 0; j < kDecTiles; ++j)
+      a[j] = *reinterpret_cast<const bf16x8_t*>(a_base + 32 * j * kActStride + 16 * s);
+#pragma unroll
+    for (int i = 0; i < kDecFeat; ++i)
+#pragma unroll
+      for (int j = 0; j < kDecTiles; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], a[j], acc[i][j], 0, 0, 0);
+  }
+}
+
 __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* __restrict__ pos_nrm, int64_t B,
                                                      const uint16_t* __restrict__ W,
                                                      const float* __restrict__ bias,
@@ -247,10 +346,15 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* 
   __shared__ __align__(16) uint16_t act[2][kDecRows * kActStride];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = int64_t(blockIdx.x) * kDecRows;
-  for (int t = threadIdx.x; t < kDecRows * RRT_MLP_IN; t += 64 * kDecWaves) {
-    const int row = t / RRT_MLP_IN, f = t % RRT_MLP_IN;
-    act[0][row * kActStride + f] =
-        r0 + row < B ? encode_feature(pos_nrm + (r0 + row) * 6, f) : uint16_t(0);
+  static_assert(kDecRows * kEncBands == 64 * kDecWaves, "one thread per (row, band)");
+  {
+    const int row = threadIdx.x / kEncBands, q = threadIdx.x % kEncBands;
+    uint16_t* dst = act[0] + row * kActStride;
+    if (r0 + row < B) {
+      encode_band(pos_nrm + (r0 + row) * 6, q, dst);
+    } else {
+      for (int f = q; f < RRT_MLP_IN; f += kEncBands) dst[f] = 0;
+    }
   }
   __syncthreads();
   const int n0 = 32 * kDecFeat * wave;
@@ -264,27 +368,10 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* 
   for (int l = 0; l < RRT_MLP_WEIGHTS; ++l) {
     const int K = l == 0 ? RRT_MLP_IN : RRT_MLP_HIDDEN;
     float16_t acc[kDecFeat][kDecTiles];
-#pragma unroll
-    for (int i = 0; i < kDecFeat; ++i)
-#pragma unroll
-      for (int j = 0; j < kDecTiles; ++j) acc[i][j] = float16_t{};
-    const uint16_t* a_base = act[cur] + ml * kActStride + 8 * (lane >> 5);
-    const uint16_t* w_base = Wl + int64_t(n0 + ml) * K + 8 * (lane >> 5);
-#pragma unroll 8
-    for (int ks = 0; ks < K; ks += 16) {
-      bf16x8_t w[kDecFeat], a[kDecTiles];
-#pragma unroll
-      for (int i = 0; i < kDecFeat; ++i)
-        w[i] = *reinterpret_cast<const bf16x8_t*>(w_base + int64_t(32 * i) * K + ks);
-#pragma unroll
-      for (int j = 0; j < kDecTiles; ++j)
-        a[j] = *reinterpret_cast<const bf16x8_t*>(a_base + 32 * j * kActStride + ks);
-#pragma unroll
-      for (int i = 0; i < kDecFeat; ++i)
-#pragma unroll
-        for (int j = 0; j < kDecTiles; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], a[j], acc[i][j], 0, 0, 0);
-    }
+    if (l == 0)
+      decode_products<RRT_MLP_IN>(act[cur], Wl, n0, lane, acc);
+    else
+      decode_products<RRT_MLP_HIDDEN>(act[cur], Wl, n0, lane, acc);
     if (l < RRT_MLP_WEIGHTS - 1) {
       uint16_t* nxt = act[cur ^ 1];
 #pragma unroll
@@ -534,8 +621,14 @@ int launch_mlp_decode(const void* w, const float* b, const float* scale, int C,
   return check_launch("decode");
 }
 
+int launch_mlp_pack(const void* w, void* out, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3(blocks(RRT_MLP_WEIGHT_COUNT / 8)), dim3(256), 0, s,
+                     static_cast<const uint16_t*>(w), static_cast<uint16_t*>(out));
+  return check_launch("mlp_pack");
+}
+
 int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s) {
-  hipLaunchKernelGGL(encode_kernel, dim3(blocks(B * RRT_MLP_IN)), dim3(256), 0, s, in,
+  hipLaunchKernelGGL(encode_kernel, dim3(blocks(B * kEncBands)), dim3(256), 0, s, in,
                      static_cast<uint16_t*>(out), B);
   return check_launch("encode");
 }

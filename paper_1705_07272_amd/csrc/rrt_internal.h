@@ -106,6 +106,7 @@ int launch_relight_order(const int32_t* idx, const int32_t* cluster, int ncluste
 // Learned decoder (mlp.hip).
 size_t mlp_workspace_bytes(int64_t B);
 int launch_mlp_encode(const float* in, int64_t B, void* out, hipStream_t s);
+int launch_mlp_pack(const void* w, void* out, hipStream_t s);
 // The whole decoder in one kernel (encode, five layers, per-slot scales):
 // out [B][256] values, bit-identical to encode + launch_mlp_forward + the
 // per-slot scaling in binary32.

@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import (RRT_MLP_BIAS_COUNT, RRT_MLP_WEIGHT_COUNT, adam_step, mlp_backward, mlp_decode,
-               mlp_encode, mlp_forward, mlp_workspace, mse, relight_mlp)
+               mlp_encode, mlp_forward, mlp_pack, mlp_workspace, mse, relight_mlp)
 
 LAYER_SHAPES = [(256, 128), (256, 256), (256, 256), (256, 256), (256, 256)]
 
@@ -63,6 +63,7 @@ class TransportDecoder:
         w, b = init_weights(seed)
         self.master = torch.from_numpy(w).to(self.device)
         self.w_bf16 = self.master.to(torch.bfloat16)
+        self._w_dec = None          # the decoder layout of w_bf16, made on first use
         self.bias = torch.from_numpy(b).to(self.device)
         self.mw = torch.zeros_like(self.master)
         self.vw = torch.zeros_like(self.master)
@@ -85,6 +86,7 @@ class TransportDecoder:
         ws = mlp_workspace(batch, self.device)
         out = torch.empty((batch, 256), dtype=torch.float32, device=self.device)
         losses = []
+        self._w_dec = None
         for s in range(steps):
             sel = torch.randint(0, V, (batch,), generator=g).to(self.device)
             x = x_all[sel].contiguous()
@@ -100,11 +102,18 @@ class TransportDecoder:
                 losses.append((s, loss.item()))
         return losses
 
+    def w_dec(self):
+        """The BF16 weights in the decoder layout (rrt_mlp_pack), packed once
+        after training."""
+        if self._w_dec is None:
+            self._w_dec = mlp_pack(self.w_bf16)
+        return self._w_dec
+
     def decode(self, inputs, clusters):
         """Coefficient values [V, 256] float32 on each vertex's cluster support
         (rrt_mlp_decode: the network and the per-slot scales in one kernel;
         0 for a cluster outside [0, C))."""
-        return mlp_decode(self.w_bf16, self.bias, self.scales,
+        return mlp_decode(self.w_dec(), self.bias, self.scales,
                           inputs.to(self.device).contiguous(),
                           clusters.to(self.device, torch.int32).contiguous())
 
@@ -112,7 +121,7 @@ class TransportDecoder:
                 out=None, workspace=None):
         """Decode and relight in one library call (rrt_relight_mlp): radiance
         [F, V] with each vertex's values decoded on its cluster's support."""
-        return relight_mlp(n, light_idx, light_val, vert_rot, self.w_bf16, self.bias,
+        return relight_mlp(n, light_idx, light_val, vert_rot, self.w_dec(), self.bias,
                            self.supports, self.scales, inputs, clusters, frame_rot=frame_rot,
                            out=out, workspace=workspace)
 

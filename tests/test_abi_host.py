@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(rrt):
 
 def test_version_and_strings(rrt):
     lib = rrt.lib
-    assert lib.rrt_abi_version() == 4
+    assert lib.rrt_abi_version() == 5
     assert lib.rrt_status_string(0) == b"ok"
     assert lib.rrt_status_string(3) == b"workspace too small"
     assert lib.rrt_status_string(99) == b"unknown status"
@@ -224,14 +224,22 @@ def test_mlp_validation(rrt):
     assert lib.rrt_mlp_backward(_p(8), _p(8), 0, _p(8), _p(8), _p(8), _p(256), 1 << 30, None) == E.RRT_ERR_INVALID
     assert lib.rrt_mse(_p(0), _p(8), 10, _p(8), _p(8), None) == E.RRT_ERR_INVALID
     # whole-decoder inference: no workspace, clusters >= 1, every pointer
-    dec = lambda w=8, C=4, pos=8, clu=8, B=10, out=8: lib.rrt_mlp_decode(  # noqa: E731
+    dec = lambda w=16, C=4, pos=8, clu=8, B=10, out=8: lib.rrt_mlp_decode(  # noqa: E731
         _p(w), _p(8), _p(8), C, _p(pos), _p(clu), B, _p(out), None)
     assert dec(C=0) == E.RRT_ERR_INVALID
     assert dec(w=0) == E.RRT_ERR_INVALID
+    assert dec(w=24) == E.RRT_ERR_INVALID        # decoder weights 16-byte aligned
     assert dec(clu=0) == E.RRT_ERR_INVALID
     assert dec(out=0) == E.RRT_ERR_INVALID
     assert dec(B=-1) == E.RRT_ERR_INVALID
     assert dec(B=0, w=0, pos=0, clu=0, out=0) == E.RRT_OK
+    # decoder layout: both buffers, 16-byte aligned, not overlapping
+    n = 2 * E.RRT_MLP_WEIGHT_COUNT
+    assert lib.rrt_mlp_pack(_p(0), _p(1 << 24), None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_pack(_p(1 << 24), _p(0), None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_pack(_p(1 << 24), _p((1 << 24) + n - 16), None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_pack(_p((1 << 24) + n - 16), _p(1 << 24), None) == E.RRT_ERR_INVALID
+    assert lib.rrt_mlp_pack(_p(1 << 24), _p((1 << 26) + 8), None) == E.RRT_ERR_INVALID
     f = ctypes.c_float
     assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(0.9), f(0.999), f(1e-8), 0, None) == E.RRT_ERR_INVALID
     assert lib.rrt_adam_step(_p(8), None, _p(8), _p(8), _p(8), 10, f(1e-3), f(1.0), f(0.999), f(1e-8), 1, None) == E.RRT_ERR_INVALID
@@ -336,8 +344,9 @@ def test_relight_mlp_validation(rrt):
                                    None if M is None else ctypes.byref(M), _p(pos), _p(clu), nvert,
                                    _p(8), flags, _p(256), wsb, None)
 
-    good = E.Mlp(8, 8, 8, 8, 4)
+    good = E.Mlp(16, 8, 8, 8, 4)
     assert call(None) == E.RRT_ERR_INVALID
+    assert call(E.Mlp(8, 8, 8, 8, 4)) == E.RRT_ERR_INVALID      # weights 16-byte aligned
     assert call(E.Mlp(8, 8, 8, 8, 0)) == E.RRT_ERR_INVALID
     assert call(E.Mlp(0, 8, 8, 8, 4)) == E.RRT_ERR_INVALID
     assert call(good, pos=0) == E.RRT_ERR_INVALID

@@ -56,6 +56,28 @@ def test_encode(rrt):
     assert np.all(got[:, 102:] == 0)
 
 
+def test_pack_layout(rrt):
+    """rrt_mlp_pack reorders the row-major weights into the documented
+    decoder layout, value for value: layer by layer at the same offsets, the
+    operand of rows 32 t.. and inputs 16 s.. at (t K / 16 + s) 512, lane
+    m + 32 h holding w[32 t + m][16 s + 8 h + e] at 8 (m + 32 h) + e."""
+    rng = np.random.default_rng(11)
+    bits = rng.integers(0, 1 << 16, rrt.RRT_MLP_WEIGHT_COUNT, dtype=np.uint16)
+    w = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+    got = rrt.mlp_pack(w).view(torch.int16).cpu().numpy().view(np.uint16)
+    want = np.empty_like(bits)
+    base = 0
+    for K in (128, 256, 256, 256, 256):
+        W = bits[base:base + 256 * K].reshape(256, K)
+        S = K // 16
+        # [t, s, h, m, e] <- W[32 t + m, 16 s + 8 h + e]
+        frag = W.reshape(8, 32, S, 2, 8).transpose(0, 2, 3, 1, 4)
+        want[base:base + 256 * K] = frag.ravel()
+        base += 256 * K
+    assert base == rrt.RRT_MLP_WEIGHT_COUNT
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("B", [1, 64, 1000, 20000])
 def test_decode_kernel_equals_layered_forward(rrt, B):
     """rrt_mlp_decode (encoding, five layers and per-slot scales in one
@@ -73,7 +95,7 @@ def test_decode_kernel_equals_layered_forward(rrt, B):
     cluster[7::89] = C
     scales = rng.uniform(0.5, 2.0, size=(C, 256)).astype(np.float32)
     xd, cd, sd = (torch.from_numpy(a).cuda() for a in (x, cluster, scales))
-    got = rrt.mlp_decode(w_dev, b_dev, sd, xd, cd)
+    got = rrt.mlp_decode(rrt.mlp_pack(w_dev), b_dev, sd, xd, cd)
     net = rrt.mlp_forward(w_dev, b_dev, rrt.mlp_encode(xd))
     ok = (cd >= 0) & (cd < C)
     want = torch.where(ok[:, None], net * sd[cd.clamp(0, C - 1).long()], torch.zeros_like(net))
