@@ -260,26 +260,32 @@ __global__ void pack_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict
   *reinterpret_cast<uint4*>(out + base + p * 8) = v;
 }
 
-// The whole decoder for a tile of kDecRows vertices in one 256-thread
-// workgroup: encoding, the four hidden layers and the output layer, with
-// the tile's activations kept in LDS (two bfloat16 buffers, k-contiguous
-// rows) and the weights read from global memory (592 KB shared by every
-// tile: an L2-resident stream).  Wave w computes output features
-// [64 w, 64 w + 64) of every layer for the tile's 64 vertices as the
-// transposed product W A^T: 2 x 2 tiles of 32 x 32 MFMAs with the weights
-// as the first operand, so that each lane ends with four consecutive
-// features of one vertex per register group and stores them with one 8-byte
-// LDS write (or one 16-byte global write for the output).  The k steps, the
-// products and their order are those of gemm_bf16 (a product of two
-// operands is the same either way round), and so are the epilogues (bias +
-// GELU rounded to bfloat16; bias, then the per-slot scale of the vertex's
-// cluster for the output): the values are bit-identical to encode + five
-// gemm_bf16 launches + the per-slot scaling in binary32.
+// The whole decoder for a tile of kDecRows = 64 vertices in one 512-thread
+// workgroup (8 waves): encoding, the four hidden layers and the output
+// layer, with the tile's activations kept in LDS (two bfloat16 buffers,
+// k-contiguous rows) and the weights read from global memory in the
+// decoder layout (592 KB shared by every tile: an L2-resident stream).
+// Wave w computes output features [32 w, 32 w + 32) of every layer for the
+// tile's 64 vertices as the transposed product W A^T: 1 x 2 tiles of
+// 32 x 32 MFMAs with the weights as the first operand, so that each lane
+// ends with four consecutive features of one vertex per register group and
+// stores them with one 8-byte LDS write.  The output layer goes through
+// LDS as float rows so that each wave writes whole 1 KiB rows of the
+// result.  The k steps, the products and their order are those of gemm_bf16
+// (a product of two operands is the same either way round), and so are
+// the epilogues (bias + GELU rounded to bfloat16; bias, then the per-slot
+// scale of the vertex's cluster for the output): the values are
+// bit-identical to encode + five gemm_bf16 launches + the per-slot scaling
+// in binary32.
 constexpr int kDecRows = 64;
 constexpr int kDecTiles = kDecRows / 32;  // 32-vertex MFMA tiles per workgroup
 constexpr int kDecWaves = 8;                // waves per workgroup
 constexpr int kDecFeat = RRT_MLP_HIDDEN / 32 / kDecWaves;  // 32-feature tiles per wave
 constexpr int kActStride = RRT_MLP_HIDDEN + 8;  // bf16 per LDS row (staggered banks)
+constexpr int kOutStride = RRT_MLP_OUT + 4;      // float per LDS output row (staggered banks)
+static_assert(kDecRows * kOutStride * 4 <= 2 * kDecRows * kActStride * 2,
+              "the output tile fits the two activation buffers");
+static_assert(RRT_MLP_OUT == 4 * 64, "one float4 per lane and output row");
 
 // One layer's products for the tile: acc[i][j] = W rows [n0 + 32 i, +32) x
 // the tile's activations of vertices [32 j, +32), over k = 0..K-1 in steps of
@@ -393,28 +399,34 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* 
       __syncthreads();
       cur ^= 1;
     } else {
+      // output layer: acc + bias of the whole tile into LDS (float rows of
+      // kOutStride over both activation buffers, free once every wave has
+      // read its operands), then each wave writes whole 1 KiB rows, scaled
+      // by the row's cluster (one cluster per row: a uniform load)
+      __syncthreads();
+      float* outl = reinterpret_cast<float*>(&act[0][0]);
 #pragma unroll
-      for (int j = 0; j < kDecTiles; ++j) {
-        const int m = 32 * j + ml;
-        if (r0 + m >= B) continue;
-        const int c = cluster[r0 + m];
-        const bool ok = c >= 0 && c < C;
-        float* orow = out + (r0 + m) * RRT_MLP_OUT;
+      for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
-        for (int i = 0; i < kDecFeat; ++i)
+        for (int g = 0; g < 4; ++g) {
+          const int n = n0 + 32 * i + 8 * g + fl;
+          const float4 b4 = *reinterpret_cast<const float4*>(bl + n);
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int n = n0 + 32 * i + 8 * g + fl;
-            const float4 b4 = *reinterpret_cast<const float4*>(bl + n);
-            float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (ok) {
-              const float4 s4 = *reinterpret_cast<const float4*>(scale + int64_t(c) * RRT_MLP_OUT + n);
-              o = make_float4((acc[i][j][4 * g] + b4.x) * s4.x, (acc[i][j][4 * g + 1] + b4.y) * s4.y,
-                              (acc[i][j][4 * g + 2] + b4.z) * s4.z,
-                              (acc[i][j][4 * g + 3] + b4.w) * s4.w);
-            }
-            *reinterpret_cast<float4*>(orow + n) = o;
-          }
+          for (int j = 0; j < kDecTiles; ++j)
+            *reinterpret_cast<float4*>(outl + (32 * j + ml) * kOutStride + n) =
+                make_float4(acc[i][j][4 * g] + b4.x, acc[i][j][4 * g + 1] + b4.y,
+                            acc[i][j][4 * g + 2] + b4.z, acc[i][j][4 * g + 3] + b4.w);
+        }
+      __syncthreads();
+      for (int row = wave; row < kDecRows && r0 + row < B; row += kDecWaves) {
+        const int c = cluster[r0 + row];
+        const float4 v = *reinterpret_cast<const float4*>(outl + row * kOutStride + 4 * lane);
+        float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (c >= 0 && c < C) {
+          const float4 s4 = *reinterpret_cast<const float4*>(scale + int64_t(c) * RRT_MLP_OUT + 4 * lane);
+          o = make_float4(v.x * s4.x, v.y * s4.y, v.z * s4.z, v.w * s4.w);
+        }
+        *reinterpret_cast<float4*>(out + (r0 + row) * RRT_MLP_OUT + 4 * lane) = o;
       }
     }
     Wl += int64_t(K) * RRT_MLP_HIDDEN;
