@@ -43,10 +43,13 @@ __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float
 // GELU with the tanh approximation, written with the identity
 // (1 + tanh u) / 2 = 1 / (1 + exp(-2u)): gelu(z) = z sigma(2u),
 // u = sqrt(2/pi) (z + 0.044715 z^3); its derivative is
-// sigma + 2 z sigma (1 - sigma) du/dz.
+// sigma + 2 z sigma (1 - sigma) du/dz.  exp(-2u) is evaluated as
+// 2^(t kGeluExp2), t = z + 0.044715 z^3, with the three constant factors
+// folded into one (one product and the hardware 2^x).
+constexpr float kGeluExp2 = -2.302208198144325f;  // -2 sqrt(2/pi) log2(e)
 __device__ __forceinline__ float gelu_sigma(float z) {
-  const float u = kSqrt2OverPi * (z + kGeluC * z * z * z);
-  return __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+  const float t = z + kGeluC * z * z * z;
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t * kGeluExp2));
 }
 __device__ __forceinline__ float gelu_f(float z) { return z * gelu_sigma(z); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
@@ -195,10 +198,13 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
 
 // Band q of gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k = 0..7) of the 6
 // inputs at `in`, rounded to bfloat16 into the feature row `row`: the six
-// sines (features 6 + 12 q + i) and cosines (6 + 12 q + 6 + i) of one
-// argument each (one shared range reduction), band 0 also the inputs
-// themselves (features 0..5); band q writes the zero padding of features
-// 102 + 4 q .. 102 + 4 q + 3 below 128.  The six inputs are loaded together.
+// sines (features 6 + 12 q + i) and cosines (6 + 12 q + 6 + i), band 0 also
+// the inputs themselves (features 0..5); band q writes the zero padding of
+// features 102 + 4 q .. 102 + 4 q + 3 below 128.  The six inputs are loaded
+// together.  2^q pi x is r = 2^(q-1) x revolutions (an exact power-of-two
+// product); r - rint(r) is exact and within half a revolution, and the
+// hardware sine and cosine of revolutions take it from there (absolute
+// error far below the bfloat16 rounding of the features).
 constexpr int kEncBands = 8;
 static_assert(6 + 12 * kEncBands + 4 * (kEncBands - 1) >= RRT_MLP_IN, "padding per band");
 
@@ -207,13 +213,13 @@ __device__ __forceinline__ void encode_band(const float* __restrict__ in, int q,
   float x[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) x[i] = in[i];
-  const float w = float(1 << q) * 3.14159265358979323846f;
+  const float rev = 0.5f * float(1 << q);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    float sn, cs;
-    sincosf(w * x[i], &sn, &cs);
-    row[6 + 12 * q + i] = bf16_bits(sn);
-    row[6 + 12 * q + 6 + i] = bf16_bits(cs);
+    const float r = x[i] * rev;
+    const float f = r - __builtin_rintf(r);
+    row[6 + 12 * q + i] = bf16_bits(__builtin_amdgcn_sinf(f));
+    row[6 + 12 * q + 6 + i] = bf16_bits(__builtin_amdgcn_cosf(f));
   }
   if (q == 0) {
 #pragma unroll
