@@ -289,8 +289,8 @@ constexpr int kDecWaves = 8;                // waves per workgroup
 constexpr int kDecFeat = RRT_MLP_HIDDEN / 32 / kDecWaves;  // 32-feature tiles per wave
 constexpr int kActStride = RRT_MLP_HIDDEN + 8;  // bf16 per LDS row (staggered banks)
 constexpr int kOutStride = RRT_MLP_OUT + 4;      // float per LDS output row (staggered banks)
-static_assert(kDecRows * kOutStride * 4 <= 2 * kDecRows * kActStride * 2,
-              "the output tile fits the two activation buffers");
+static_assert(32 * kOutStride * 4 <= kDecRows * kActStride * 2,
+              "a 32-vertex output tile fits the activation buffer");
 static_assert(RRT_MLP_OUT == 4 * 64, "one float4 per lane and output row");
 
 // One layer's products for the tile: acc[i][j] = W rows [n0 + 32 i, +32) x
@@ -301,7 +301,7 @@ static_assert(RRT_MLP_OUT == 4 * 64, "one float4 per lane and output row");
 // that that many loads are in flight while the products run instead of
 // each step waiting for its own.  K is a compile-time constant so that the
 // loop and the ring unroll.
-constexpr int kDecAhead = 8;
+constexpr int kDecAhead = 2;
 
 template <int K>
 __device__ __forceinline__ void decode_products(const uint16_t* __restrict__ act,
@@ -349,19 +349,19 @@ __device__ __forceinline__ void decode_products(const uint16_t* __restrict__ act
   }
 }
 
-__global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* __restrict__ pos_nrm, int64_t B,
+__global__ __launch_bounds__(64 * kDecWaves, 6) void decode_kernel(const float* __restrict__ pos_nrm, int64_t B,
                                                      const uint16_t* __restrict__ W,
                                                      const float* __restrict__ bias,
                                                      const int32_t* __restrict__ cluster,
                                                      const float* __restrict__ scale, int C,
                                                      float* __restrict__ out) {
-  __shared__ __align__(16) uint16_t act[2][kDecRows * kActStride];
+  __shared__ __align__(16) uint16_t act[kDecRows * kActStride];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = int64_t(blockIdx.x) * kDecRows;
   static_assert(kDecRows * kEncBands == 64 * kDecWaves, "one thread per (row, band)");
   {
     const int row = threadIdx.x / kEncBands, q = threadIdx.x % kEncBands;
-    uint16_t* dst = act[0] + row * kActStride;
+    uint16_t* dst = act + row * kActStride;
     if (r0 + row < B) {
       encode_band(pos_nrm + (r0 + row) * 6, q, dst);
     } else {
@@ -373,7 +373,6 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* 
   // register r of tile (i, j): feature n0 + 32 i + 8 (r / 4) + 4 (lane / 32) + r % 4,
   // vertex 32 j + lane % 32
   const int fl = 4 * (lane >> 5), ml = lane & 31;
-  int cur = 0;
   const uint16_t* Wl = W;
   const float* bl = bias;
 #pragma unroll 1
@@ -381,11 +380,11 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* 
     const int K = l == 0 ? RRT_MLP_IN : RRT_MLP_HIDDEN;
     float16_t acc[kDecFeat][kDecTiles];
     if (l == 0)
-      decode_products<RRT_MLP_IN>(act[cur], Wl, n0, lane, acc);
+      decode_products<RRT_MLP_IN>(act, Wl, n0, lane, acc);
     else
-      decode_products<RRT_MLP_HIDDEN>(act[cur], Wl, n0, lane, acc);
+      decode_products<RRT_MLP_HIDDEN>(act, Wl, n0, lane, acc);
+    __syncthreads();  // every wave has read its operands: the buffer is free
     if (l < RRT_MLP_WEIGHTS - 1) {
-      uint16_t* nxt = act[cur ^ 1];
 #pragma unroll
       for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
@@ -399,40 +398,40 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void decode_kernel(const float* 
             v.x = bf16x2_bits(gelu_f(acc[i][j][4 * g] + b4.x), gelu_f(acc[i][j][4 * g + 1] + b4.y));
             v.y = bf16x2_bits(gelu_f(acc[i][j][4 * g + 2] + b4.z),
                               gelu_f(acc[i][j][4 * g + 3] + b4.w));
-            *reinterpret_cast<uint2*>(nxt + m * kActStride + n) = v;
+            *reinterpret_cast<uint2*>(act + m * kActStride + n) = v;
           }
         }
       __syncthreads();
-      cur ^= 1;
     } else {
-      // output layer: acc + bias of the whole tile into LDS (float rows of
-      // kOutStride over both activation buffers, free once every wave has
-      // read its operands), then each wave writes whole 1 KiB rows, scaled
-      // by the row's cluster (one cluster per row: a uniform load)
-      __syncthreads();
-      float* outl = reinterpret_cast<float*>(&act[0][0]);
+      // output layer, one 32-vertex tile at a time: acc + bias into LDS
+      // (float rows of kOutStride), then each wave writes whole 1 KiB rows,
+      // scaled by the row's cluster (one cluster per row: a uniform load)
+      float* outl = reinterpret_cast<float*>(act);
 #pragma unroll
-      for (int i = 0; i < kDecFeat; ++i)
+      for (int j = 0; j < kDecTiles; ++j) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int n = n0 + 32 * i + 8 * g + fl;
-          const float4 b4 = *reinterpret_cast<const float4*>(bl + n);
+        for (int i = 0; i < kDecFeat; ++i)
 #pragma unroll
-          for (int j = 0; j < kDecTiles; ++j)
-            *reinterpret_cast<float4*>(outl + (32 * j + ml) * kOutStride + n) =
+          for (int g = 0; g < 4; ++g) {
+            const int n = n0 + 32 * i + 8 * g + fl;
+            const float4 b4 = *reinterpret_cast<const float4*>(bl + n);
+            *reinterpret_cast<float4*>(outl + ml * kOutStride + n) =
                 make_float4(acc[i][j][4 * g] + b4.x, acc[i][j][4 * g + 1] + b4.y,
                             acc[i][j][4 * g + 2] + b4.z, acc[i][j][4 * g + 3] + b4.w);
+          }
+        __syncthreads();
+        const int64_t rj = r0 + 32 * j;
+        for (int row = wave; row < 32 && rj + row < B; row += kDecWaves) {
+          const int c = cluster[rj + row];
+          const float4 v = *reinterpret_cast<const float4*>(outl + row * kOutStride + 4 * lane);
+          float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          if (c >= 0 && c < C) {
+            const float4 s4 = *reinterpret_cast<const float4*>(scale + int64_t(c) * RRT_MLP_OUT + 4 * lane);
+            o = make_float4(v.x * s4.x, v.y * s4.y, v.z * s4.z, v.w * s4.w);
+          }
+          *reinterpret_cast<float4*>(out + (rj + row) * RRT_MLP_OUT + 4 * lane) = o;
         }
-      __syncthreads();
-      for (int row = wave; row < kDecRows && r0 + row < B; row += kDecWaves) {
-        const int c = cluster[r0 + row];
-        const float4 v = *reinterpret_cast<const float4*>(outl + row * kOutStride + 4 * lane);
-        float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (c >= 0 && c < C) {
-          const float4 s4 = *reinterpret_cast<const float4*>(scale + int64_t(c) * RRT_MLP_OUT + 4 * lane);
-          o = make_float4(v.x * s4.x, v.y * s4.y, v.z * s4.z, v.w * s4.w);
-        }
-        *reinterpret_cast<float4*>(out + (r0 + row) * RRT_MLP_OUT + 4 * lane) = o;
+        if (j + 1 < kDecTiles) __syncthreads();
       }
     }
     Wl += int64_t(K) * RRT_MLP_HIDDEN;
