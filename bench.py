@@ -555,7 +555,7 @@ def run_learned(args, w):
         "roofline_decode": {"bound": "mfma", "achieved": round(dec_tflops, 2),
                             "peak": 2500.0, "unit": "TFLOP/s",
                             "frac": round(dec_tflops / 2500.0, 4),
-                            "kernel": "encode + 5 BF16 MFMA GEMMs + scaling",
+                            "kernel": "decode_kernel (encoding, 5 BF16 MFMA layers, scaling)",
                             "kernel_ms": round(ms_dec, 4), "flops": flops},
         "cpu_baseline": base,
     }), flush=True)
