@@ -211,6 +211,63 @@ def test_full_cube128_v50000_triple_product(rrt):
     assert err <= 1e-5
 
 
+def _full_launch_rows(rrt, w, sample):
+    """Checker-made rows and inputs of the sampled vertices, placed into the
+    device rows of the full 50,000-vertex launch."""
+    from cases import build_case
+    case = build_case(w, sample)
+    idx, val = _device_rows(rrt, w)
+    sel = torch.from_numpy(sample).cuda().long()
+    idx[sel] = torch.from_numpy(case["t_idx"]).cuda()
+    val[sel] = torch.from_numpy(case["t_val"]).cuda()
+    return case, idx, val
+
+
+def test_full_cube128_v50000_chain_rule(rrt):
+    """The benchmark launch with the chain-rule phase shift (row f1): 96
+    sampled outputs of the full launch against the checker's chain-rule
+    rotation on the same stored inputs, rel-L2 <= 1e-5."""
+    from cases import frame_errors
+    from oracle.chain import relight_chain
+    from scenes.scene import WORKLOADS, vertex_rotations
+    w = WORKLOADS[2]
+    sample = _sample(w.nverts, 96, 5)
+    case, idx, val = _full_launch_rows(rrt, w, sample)
+    out = rrt.relight(w.n, torch.from_numpy(case["light_idx"]).cuda(),
+                      torch.from_numpy(case["light_val"]).cuda(),
+                      torch.from_numpy(vertex_rotations(w)).cuda(), idx, val, chain_rule=True)
+    torch.cuda.synchronize()
+    ref = relight_chain(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
+                        case["t_idx"], case["t_val"])
+    err = max(frame_errors(out.cpu().numpy()[:, sample], ref))
+    print(f"cube128 V=50000 chain rule: sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_full_cube128_v50000_coarse_start(rrt, levels):
+    """The benchmark launch started `levels` levels below the finest one
+    (row f3: lighting and rows re-indexed on the device, rotation at
+    n >> levels): 96 sampled outputs against the checker's coarse-level start
+    on the same stored inputs, rel-L2 <= 1e-5."""
+    from cases import frame_errors
+    from oracle.levels import relight_from_level
+    from scenes.scene import WORKLOADS, vertex_rotations
+    w = WORKLOADS[2]
+    sample = _sample(w.nverts, 96, 6 + levels)
+    case, idx, val = _full_launch_rows(rrt, w, sample)
+    li = rrt.coarsen_indices(torch.from_numpy(case["light_idx"]).cuda(), w.n, levels)
+    out = rrt.relight(w.n >> levels, li, torch.from_numpy(case["light_val"]).cuda(),
+                      torch.from_numpy(vertex_rotations(w)).cuda(),
+                      rrt.coarsen_indices(idx, w.n, levels), val)
+    torch.cuda.synchronize()
+    ref = relight_from_level(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
+                             case["t_idx"], case["t_val"], levels)
+    err = max(frame_errors(out.cpu().numpy()[:, sample], ref))
+    print(f"cube128 V=50000 started {levels} levels coarser: sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5
+
+
 def test_full_latlong128_v50000(rrt):
     """Lat-long 128 x 256, top-1024 lighting, 50,000 vertices, CSR-256: the
     launch the bench times, sampled outputs against the checker."""
