@@ -45,6 +45,8 @@ constexpr int kBlock = 32;
 // Transport entries of a vertex listed in LDS; entries past this count are
 // decoded from global memory in every block.
 constexpr int kMaxListed = 512;
+// Chunks of 64 transport entries whose loads the listing issues together.
+constexpr int kListChunks = 4;
 // LDS for the FP64 block sums of the faces processed together.
 constexpr int kGroupBytes = 4096;
 // LDS bit mask of the blocks of a face group that hold listed entries (at
@@ -615,6 +617,7 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
 
   // faces touched by this vertex's transport row
   unsigned m = 0;
+#pragma unroll 4
   for (int e = lane; e < nnz; e += kThreads) {
     const int idx = idx_row ? idx_row[e] : e;
     if (idx >= 0 && idx < NF * (n << logn)) m |= 1u << (idx >> (2 * logn));
@@ -668,23 +671,37 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
           for (int k = lane; k < bwords; k += kThreads) bmask[k] = 0u;
           wave_sync();
         }
-        for (int c0 = 0; c0 < listed; c0 += kThreads) {
-          const int e = c0 + lane;
-          int key = 0, kind = -1;
-          if (e < listed) kind = classify<Q, NF>(idx_row ? idx_row[e] : e, logn, G, faces, g0, FG, key);
-          const uint64_t bf = __ballot(kind == 0), bc = __ballot(kind == 1);
-          if (kind >= 0) {
-            const int at = kind == 0 ? nfine + __popcll(bf & lanes_below)
-                                     : listed - 1 - (ncoarse + __popcll(bc & lanes_below));
-            lkey[at] = key;
-            lval[at] = transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e);
-            if (SUM_ONLY && kind == 0) {
-              const int gb = (key >> kOffBits) & ((1 << kBlockBits) - 1);
-              atomicOr(&bmask[gb >> 5], 1u << (gb & 31));
-            }
+        for (int c0 = 0; c0 < listed; c0 += kListChunks * kThreads) {
+          // the entries of kListChunks chunks of 64 are loaded first, so
+          // that their loads are in flight together, then each chunk is
+          // classified and listed (a chunk past `listed` lists nothing)
+          int ix[kListChunks];
+          float vx[kListChunks];
+#pragma unroll
+          for (int u = 0; u < kListChunks; ++u) {
+            const int e = c0 + u * kThreads + lane;
+            ix[u] = e < listed ? (idx_row ? idx_row[e] : e) : -1;
+            vx[u] = e < listed ? transport_value(p.tval, p.tscale, p.dtype, v, p.nnz, e) : 0.0f;
           }
-          nfine += __popcll(bf);
-          ncoarse += __popcll(bc);
+#pragma unroll
+          for (int u = 0; u < kListChunks; ++u) {
+            const int e = c0 + u * kThreads + lane;
+            int key = 0, kind = -1;
+            if (e < listed) kind = classify<Q, NF>(ix[u], logn, G, faces, g0, FG, key);
+            const uint64_t bf = __ballot(kind == 0), bc = __ballot(kind == 1);
+            if (kind >= 0) {
+              const int at = kind == 0 ? nfine + __popcll(bf & lanes_below)
+                                       : listed - 1 - (ncoarse + __popcll(bc & lanes_below));
+              lkey[at] = key;
+              lval[at] = vx[u];
+              if (SUM_ONLY && kind == 0) {
+                const int gb = (key >> kOffBits) & ((1 << kBlockBits) - 1);
+                atomicOr(&bmask[gb >> 5], 1u << (gb & 31));
+              }
+            }
+            nfine += __popcll(bf);
+            ncoarse += __popcll(bc);
+          }
         }
         wave_sync();
       }
