@@ -158,25 +158,26 @@ def decode_storage(form, codes, scale, nnz):
 
 
 def _rows_and_reference_job(args):
-    w, vids, li, lv, rot, frot = args
+    w, vids, li, lv, rot, frot, frames = args
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         idx, val = stored_transport(w, vids)
         case = dict(n=w.n, light_idx=li, light_val=lv, vert_rot=rot, frame_rot=frot, t_idx=idx,
                     t_val=val)
-        ref, mag = reference(case, return_scale=True)
+        ref, mag = reference(case, frames=frames, return_scale=True)
     return idx, val, ref, mag
 
 
-def rows_and_reference(w, vids, li, lv, rot, frot, workers=8):
+def rows_and_reference(w, vids, li, lv, rot, frot, workers=8, frames=None):
     """stored_transport rows of the vertices `vids` and the checker's
-    (radiance, magnitude scale) [F, len(vids)] for them, over `workers`
-    fresh processes (spawned: this process may hold a GPU context)."""
+    (radiance, magnitude scale) [F, len(vids)] for them (F: every frame, or
+    the listed `frames`), over `workers` fresh processes (spawned: this
+    process may hold a GPU context)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     vids = np.asarray(vids)
     chunks = [c for c in np.array_split(np.arange(len(vids)), 4 * workers) if len(c)]
-    jobs = [(w, vids[c], li, lv, rot[c], frot) for c in chunks]
+    jobs = [(w, vids[c], li, lv, rot[c], frot, frames) for c in chunks]
     with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
         parts = list(ex.map(_rows_and_reference_job, jobs))
     idx = np.concatenate([p[0] for p in parts])
