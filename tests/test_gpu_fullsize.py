@@ -270,12 +270,15 @@ def test_full_cube128_v50000_coarse_start(rrt, levels):
 
 def test_full_latlong128_v50000(rrt):
     """Lat-long 128 x 256, top-1024 lighting, 50,000 vertices, CSR-256: the
-    launch the bench times, sampled outputs against the checker."""
+    launch the bench times, 512 sampled outputs against the checker, every
+    element within the FP32 element bound (a source texel one column off
+    at a binary32 tie of the rule moves a vertex by about 1e-4 of its
+    magnitude, far outside it) and rel-L2 <= 1e-5."""
     from cases import frame_errors, latlong_case
     from oracle.latlong import relight_latlong
     from scenes.latlong import LATLONG_WORKLOADS, phong_exponents, rotations, transport_pixels_torch
     w = LATLONG_WORKLOADS[6]
-    sample = _sample(w.nverts, 40, 6)
+    sample = _sample(w.nverts, 512, 6)
     case = latlong_case(w, sample)
     exps = phong_exponents(w)
     idx = torch.empty((w.nverts, w.nnz), dtype=torch.int32, device="cuda")
@@ -292,10 +295,13 @@ def test_full_latlong128_v50000(rrt):
                               torch.from_numpy(case["light_val"]).cuda(),
                               torch.from_numpy(elev).cuda(), torch.from_numpy(shift).cuda(), idx, val)
     torch.cuda.synchronize()
-    ref = relight_latlong(case["light_idx"], case["light_val"], w.H, case["elev"], case["shift"],
-                          case["t_idx"], case["t_val"])
-    err = max(frame_errors(out.cpu().numpy()[None, sample], ref))
-    print(f"latlong 128x256 V=50000 sampled rel-L2 {err:.3e}")
+    ref, mag = relight_latlong(case["light_idx"], case["light_val"], w.H, case["elev"],
+                               case["shift"], case["t_idx"], case["t_val"], return_scale=True)
+    got = out.cpu().numpy()[None, sample].astype(np.float64)
+    bound = 1e-5 * np.abs(ref) + 2e-7 * mag
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
+    err = max(frame_errors(got, ref))
+    print(f"latlong 128x256 V=50000, 512 sampled vertices: rel-L2 {err:.3e}")
     assert err <= 1e-5
 
 
