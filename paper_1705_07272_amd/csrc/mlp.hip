@@ -268,16 +268,18 @@ __global__ void pack_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict
 
 // The whole decoder for a tile of kDecRows = 64 vertices in one 512-thread
 // workgroup (8 waves): encoding, the four hidden layers and the output
-// layer, with the tile's activations kept in LDS (two bfloat16 buffers,
-// k-contiguous rows) and the weights read from global memory in the
-// decoder layout (592 KB shared by every tile: an L2-resident stream).
+// layer, with the tile's activations kept in LDS (one bfloat16 buffer of
+// k-contiguous rows, 33.8 KB, rewritten in place between two barriers after
+// each layer's products, so that three workgroups share a CU) and the
+// weights read from global memory in the decoder layout (592 KB shared by
+// every tile: an L2-resident stream).
 // Wave w computes output features [32 w, 32 w + 32) of every layer for the
 // tile's 64 vertices as the transposed product W A^T: 1 x 2 tiles of
 // 32 x 32 MFMAs with the weights as the first operand, so that each lane
 // ends with four consecutive features of one vertex per register group and
 // stores them with one 8-byte LDS write.  The output layer goes through
-// LDS as float rows so that each wave writes whole 1 KiB rows of the
-// result.  The k steps, the products and their order are those of gemm_bf16
+// LDS as float rows, 32 vertices at a time, so that each wave writes whole
+// 1 KiB rows of the result.  The k steps, the products and their order are those of gemm_bf16
 // (a product of two operands is the same either way round), and so are
 // the epilogues (bias + GELU rounded to bfloat16; bias, then the per-slot
 // scale of the vertex's cluster for the output): the values are
