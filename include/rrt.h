@@ -62,8 +62,10 @@ extern "C" {
    slightly different source texels for general rotations).
    4: transport dtype RRT_S11 (packed 11-bit block-scaled fixed point).
    5: rrt_mlp_decode and rrt_relight_mlp take the weights in the decoder
-   layout of rrt_mlp_pack. */
-#define RRT_ABI_VERSION 5
+   layout of rrt_mlp_pack.
+   6: the source map is binary32 for RRT_F16 lighting too (its workspace is
+   that of RRT_F32 lighting; results closer to the FP64 reference). */
+#define RRT_ABI_VERSION 6
 
 typedef enum {
   RRT_OK = 0,
@@ -158,8 +160,8 @@ typedef struct {
   const int32_t* idx;    /* [k] flat coefficient indices (any order; out-of-range
                             entries ignored; duplicates: one of them wins) */
   const void* val;       /* [k] values, dtype RRT_F32 or RRT_F16 */
-  int dtype;             /* rrt_dtype of val; RRT_F16 also stores the
-                            reconstructed source map in binary16 */
+  int dtype;             /* rrt_dtype of val (the source map reconstructed
+                            from the coefficients is binary32 either way) */
 } rrt_light;
 
 typedef struct {
@@ -207,11 +209,10 @@ typedef struct {
 /* R_fv = (R_q(frame f) R_q(vertex v) + 2^(k-1)) >> k, k = 22 - log2(n),
    entry-wise in exact integer arithmetic (flooring shift). */
 
-/* Workspace: the reconstructed source map (6 n^2 values, float32 or
-   binary16) plus a 6 n^2 float32 staging buffer (after prepare with
-   RRT_CHAIN_RULE: the source's 2x2 block coefficients, float32 (S, H, V, D)
-   per block), 256-byte aligned.  Only L->n and L->dtype matter for its
-   size. */
+/* Workspace: the reconstructed source map (6 n^2 float32 values) plus a
+   6 n^2 float32 staging buffer (after prepare with RRT_CHAIN_RULE: the
+   source's 2x2 block coefficients, float32 (S, H, V, D) per block),
+   256-byte aligned.  Only L->n matters for its size. */
 int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
                           unsigned flags, size_t* bytes);
 /* radiance: [F][V] float32 (frame-major).  Equivalent to
@@ -286,7 +287,7 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
  *   H: power of two in [4, 512]; transport as rrt_transport without
  *   cluster or brdf; flags: RRT_COMPENSATED only; radiance [V] float32.
  *   Workspace: rrt_relight_latlong_workspace() bytes, 256-byte aligned:
- *   [2 H^2 float32 staging][source map 2 H^2 float32|binary16][7 H float32
+ *   [2 H^2 float32 staging][source map 2 H^2 float32][7 H float32
  *   tables: sin, cos of the row centres (H each), sin, cos of the column
  *   centres (2H each), C_k (H)], each part starting 256-byte aligned.
  * --------------------------------------------------------------------- */

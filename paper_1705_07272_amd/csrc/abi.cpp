@@ -36,12 +36,15 @@ static bool transport_dtype_ok(int dtype) {
   return dtype == RRT_F32 || dtype == RRT_BF16 || block_scaled(dtype);
 }
 
-RelightWs relight_ws(int n, bool f16) {
+// The coefficient staging buffer and the FP32 source map (for either
+// lighting dtype: binary16 lighting is its coefficients' precision; the map
+// reconstructed from them is kept in binary32).
+RelightWs relight_ws(int n) {
   const size_t cells = size_t(6) * n * n;
   RelightWs w;
   w.dense_off = 0;
   w.src_off = align256(cells * sizeof(float));
-  w.total = w.src_off + align256(cells * (f16 ? sizeof(__half) : sizeof(float)));
+  w.total = w.src_off + align256(cells * sizeof(float));
   return w;
 }
 
@@ -208,7 +211,7 @@ int rrt_relight_workspace(const rrt_light* L, const rrt_rotations* R, const rrt_
   if (!bytes) return fail(RRT_ERR_INVALID, "relight_workspace: null bytes");
   const int st = validate_relight(L, R, T);
   if (st) return st;
-  *bytes = relight_ws(L->n, L->dtype == RRT_F16).total;
+  *bytes = relight_ws(L->n).total;
   return RRT_OK;
 }
 
@@ -236,21 +239,19 @@ int rrt_relight_prepare(const rrt_light* L, unsigned flags, void* ws, size_t ws_
   if (st) return st;
   st = check_relight_flags(L, flags);
   if (st) return st;
-  const bool f16 = L->dtype == RRT_F16;
-  const RelightWs w = relight_ws(L->n, f16);
+  const RelightWs w = relight_ws(L->n);
   st = check_ws(ws, ws_bytes, w.total, "relight_prepare");
   if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   float* dense = reinterpret_cast<float*>(base + w.dense_off);
-  void* src = base + w.src_off;
+  float* src = reinterpret_cast<float*>(base + w.src_off);
   st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, 6, dense, s);
   if (st) return st;
-  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, 6, s, true)
-           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 6, s, true);
+  st = launch_haar_inverse(dense, src, L->n, 6, s, true);
   if (st || !(flags & RRT_CHAIN_RULE)) return st;
   // the staging buffer is free now: it takes the 2x2 block coefficients
-  return launch_source_blocks(src, f16, L->n, dense, s);
+  return launch_source_blocks(src, L->n, dense, s);
 }
 
 int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T,
@@ -260,15 +261,13 @@ int rrt_relight_prepared(const rrt_light* L, const rrt_rotations* R, const rrt_t
   if (st) return st;
   st = check_relight_flags(L, flags, T);
   if (st) return st;
-  const bool f16 = L->dtype == RRT_F16;
-  const RelightWs w = relight_ws(L->n, f16);
+  const RelightWs w = relight_ws(L->n);
   st = check_ws(ws, ws_bytes, w.total, "relight");
   if (st) return st;
   if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight: null radiance");
   if (T->nvert == 0) return RRT_OK;
   RelightLaunch a;
-  a.src = static_cast<const char*>(ws) + w.src_off;
-  a.src_f16 = f16;
+  a.src = reinterpret_cast<const float*>(static_cast<const char*>(ws) + w.src_off);
   a.vert_rot = R->vert_rot;
   a.frame_rot = R->frame_rot;
   a.t_idx = T->idx;
@@ -325,7 +324,7 @@ int rrt_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport*
   if (st) return st;
   st = check_relight_flags(L, flags, T);
   if (st) return st;
-  st = check_ws(ws, ws_bytes, relight_ws(L->n, L->dtype == RRT_F16).total, "relight");
+  st = check_ws(ws, ws_bytes, relight_ws(L->n).total, "relight");
   if (st) return st;
   if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight: null radiance");
   st = rrt_relight_prepare(L, flags, ws, ws_bytes, stream);
@@ -339,12 +338,12 @@ struct LatLongWs {
   size_t dense_off, src_off, grid_off, total;
 };
 
-static LatLongWs latlong_ws(int H, bool f16) {
+static LatLongWs latlong_ws(int H) {
   const size_t cells = size_t(2) * H * H;
   LatLongWs w;
   w.dense_off = 0;
   w.src_off = align256(cells * sizeof(float));
-  w.grid_off = w.src_off + align256(cells * (f16 ? sizeof(__half) : sizeof(float)));
+  w.grid_off = w.src_off + align256(cells * sizeof(float));
   w.total = w.grid_off + align256(size_t(latlong_grid_floats(H)) * sizeof(float));
   return w;
 }
@@ -381,7 +380,7 @@ int rrt_relight_latlong_workspace(const rrt_light* L, size_t* bytes) {
   if (!L || !bytes) return fail(RRT_ERR_INVALID, "relight_latlong_workspace: null argument");
   if (!valid_n(L->n, 4) || L->n > 512)
     return fail(RRT_ERR_INVALID, "relight_latlong: H=%d not a power of two in [4,512]", L->n);
-  *bytes = latlong_ws(L->n, L->dtype == RRT_F16).total;
+  *bytes = latlong_ws(L->n).total;
   return RRT_OK;
 }
 
@@ -391,26 +390,23 @@ int rrt_relight_latlong(const rrt_light* L, const rrt_latlong_rotations* R, cons
   if (st) return st;
   if (flags & ~RRT_COMPENSATED)
     return fail(RRT_ERR_INVALID, "relight_latlong: flags 0x%x (only RRT_COMPENSATED)", flags);
-  const bool f16 = L->dtype == RRT_F16;
-  const LatLongWs w = latlong_ws(L->n, f16);
+  const LatLongWs w = latlong_ws(L->n);
   st = check_ws(ws, ws_bytes, w.total, "relight_latlong");
   if (st) return st;
   if (T->nvert > 0 && !radiance) return fail(RRT_ERR_INVALID, "relight_latlong: null radiance");
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   float* dense = reinterpret_cast<float*>(base + w.dense_off);
-  void* src = base + w.src_off;
+  float* src = reinterpret_cast<float*>(base + w.src_off);
   float* grid = reinterpret_cast<float*>(base + w.grid_off);
   st = launch_scatter_light(L->idx, L->val, L->dtype, L->k, L->n, 2, dense, s);
   if (st) return st;
-  st = f16 ? launch_haar_inverse_f16(dense, static_cast<__half*>(src), dense, L->n, 2, s)
-           : launch_haar_inverse(dense, static_cast<float*>(src), L->n, 2, s);
+  st = launch_haar_inverse(dense, src, L->n, 2, s);
   if (st) return st;
   st = launch_latlong_grid(L->n, grid, s);
   if (st || T->nvert == 0) return st;
   RelightLaunch a;
   a.src = src;
-  a.src_f16 = f16;
   a.vert_rot = nullptr;
   a.frame_rot = nullptr;
   a.t_idx = T->idx;
@@ -530,7 +526,7 @@ static int64_t mlp_chunk(int64_t nvert) {
 static RelightMlpWs relight_mlp_ws(const rrt_light* L, int64_t nvert) {
   RelightMlpWs w;
   const int64_t chunk = mlp_chunk(nvert);
-  w.relight_total = relight_ws(L->n, L->dtype == RRT_F16).total;
+  w.relight_total = relight_ws(L->n).total;
   w.values_off = w.relight_total;
   w.order_off = w.values_off + align256(size_t(chunk) * RRT_MLP_OUT * sizeof(float));
   w.order_ws_off = w.order_off + align256(size_t(chunk) * sizeof(int32_t));
@@ -620,8 +616,7 @@ int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M
                                    order, base + w.order_ws_off, s)))
       return st;
     RelightLaunch a;
-    a.src = base + relight_ws(L->n, L->dtype == RRT_F16).src_off;
-    a.src_f16 = L->dtype == RRT_F16;
+    a.src = reinterpret_cast<const float*>(base + relight_ws(L->n).src_off);
     a.vert_rot = R->vert_rot + v0 * 9;
     a.frame_rot = R->frame_rot;
     a.t_idx = M->support;
@@ -637,7 +632,7 @@ int rrt_relight_mlp(const rrt_light* L, const rrt_rotations* R, const rrt_mlp* M
     a.flags = flags;
     a.out = radiance + v0;
     a.out_stride = nvert;
-    a.blocks = base + relight_ws(L->n, L->dtype == RRT_F16).dense_off;
+    a.blocks = base + relight_ws(L->n).dense_off;
     a.brdf = nullptr;
     a.material = nullptr;
     a.nmaterials = 0;

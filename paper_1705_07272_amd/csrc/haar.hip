@@ -12,7 +12,6 @@
 // the launches through the top-left corner of the output (forward) or the
 // first texel of each output tile (inverse), positions no other coefficient
 // or texel of the first launch uses.
-#include <hip/hip_fp16.h>
 
 #include "rrt_internal.h"
 
@@ -129,24 +128,12 @@ __global__ __launch_bounds__(64) void haar_inv_coarse(const float* coef, float* 
   for (int e = threadIdx.x; e < G * G; e += 64) st[(e / G) * rs + (e % G) * cs] = s[e];
 }
 
-template <typename OutT>
-__device__ __forceinline__ OutT to_out(float x);
-template <>
-__device__ __forceinline__ float to_out<float>(float x) {
-  return x;
-}
-template <>
-__device__ __forceinline__ __half to_out<__half>(float x) {
-  return __float2half_rn(x);
-}
-
 // grid: count * 6 * G * G; the tile sum comes from coef[face][0] when G == 1,
 // else from stage[face * n * n + ty * rs + tx * cs].  With `strips` (n >= 4)
 // the pixels are written in strips of four rows, each strip column by column:
 // row r, column c of a square at ((r >> 2) << (log2 n + 2)) + 4 c + (r & 3).
-template <typename OutT>
 __global__ __launch_bounds__(kThreads) void haar_inv_tiles(const float* coef, const float* stage,
-                                                           OutT* pix, int n, int logq, int G,
+                                                           float* pix, int n, int logq, int G,
                                                            int64_t rs, int64_t cs, bool strips) {
   extern __shared__ float lds[];
   const int Q = 1 << logq;
@@ -155,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void haar_inv_tiles(const float* coef, co
   const int64_t face = blk / (G * G);
   const int ty = tile / G, tx = tile % G;
   const float* f = coef + face * int64_t(n) * n;
-  OutT* dst = pix + face * int64_t(n) * n;
+  float* dst = pix + face * int64_t(n) * n;
   if (threadIdx.x == 0)
     lds[0] = (G == 1) ? f[0] : stage[face * int64_t(n) * n + ty * rs + tx * cs];
   __syncthreads();
@@ -182,12 +169,12 @@ __global__ __launch_bounds__(kThreads) void haar_inv_tiles(const float* coef, co
     for (int e = threadIdx.x; e < Q * Q; e += kThreads) {
       const int st = e >> (logq + 2), c = (e >> 2) & (Q - 1), rl = e & 3;
       const int r = 4 * st + rl;
-      dst[int64_t((row0 + r) >> 2) * 4 * n + 4 * (col0 + c) + rl] = to_out<OutT>(lds[r * Q + c]);
+      dst[int64_t((row0 + r) >> 2) * 4 * n + 4 * (col0 + c) + rl] = lds[r * Q + c];
     }
   } else {
     for (int e = threadIdx.x; e < Q * Q; e += kThreads) {
       const int r = e >> logq, c = e & (Q - 1);
-      dst[int64_t(row0 + r) * n + col0 + c] = to_out<OutT>(lds[e]);
+      dst[int64_t(row0 + r) * n + col0 + c] = lds[e];
     }
   }
 }
@@ -222,30 +209,10 @@ int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, h
     if (st) return st;
   }
   const int64_t grid = squares * G * G;
-  hipLaunchKernelGGL(haar_inv_tiles<float>, dim3(unsigned(grid)), dim3(kThreads),
+  hipLaunchKernelGGL(haar_inv_tiles, dim3(unsigned(grid)), dim3(kThreads),
                      size_t(Q) * Q * sizeof(float), s, coef, (const float*)pix, pix, n, ilog2(Q),
                      G, rs, cs, strips);
   return check_launch("haar_inv_tiles");
-}
-
-// `coef` is the caller's own dense staging buffer: for n > 64 its Mallat
-// corner is overwritten by the tile sums (spatial order).
-int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
-                            hipStream_t s, bool strips) {
-  if (n < 4) strips = false;
-  const int Q = n < kTile ? n : kTile;
-  const int G = n / Q;
-  const int64_t rs = n, cs = 1;
-  if (G > 1) {
-    hipLaunchKernelGGL(haar_inv_coarse, dim3(unsigned(squares)), dim3(64), 0, s, coef, staging, n,
-                       G, rs, cs);
-    int st = check_launch("haar_inv_coarse");
-    if (st) return st;
-  }
-  hipLaunchKernelGGL(haar_inv_tiles<__half>, dim3(unsigned(squares * G * G)), dim3(kThreads),
-                     size_t(Q) * Q * sizeof(float), s, coef, (const float*)staging, pix, n,
-                     ilog2(Q), G, rs, cs, strips);
-  return check_launch("haar_inv_tiles_f16");
 }
 
 }  // namespace rrt

@@ -58,7 +58,7 @@ extern "C" int rrt_relight_noalloc(const rrt_light* L, const rrt_rotations* R,
   if (st) return st;
   st = check_relight_flags(L, flags, T);
   if (st) return st;
-  const size_t need = relight_ws(L->n, L->dtype == RRT_F16).total;
+  const size_t need = relight_ws(L->n).total;
   if (need > kScratchBytes)
     return fail(RRT_ERR_UNSUPPORTED,
                 "relight_noalloc: n=%d needs %zu bytes of scratch, more than the %zu held "

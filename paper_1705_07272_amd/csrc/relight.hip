@@ -63,32 +63,21 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 extern "C" __device__ float rrt_struct_load_f32(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
                                                 int soffset, int aux)
     __asm("llvm.amdgcn.struct.ptr.buffer.load.f32");
-extern "C" __device__ short rrt_struct_load_i16(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
-                                                int soffset, int aux)
-    __asm("llvm.amdgcn.struct.ptr.buffer.load.i16");
 
 // Resource over `count` elements at p, addressed with indices offset by
 // `bias` (element i of the map is index bias + i; the cube-map gather hands
 // texel_bias-offset indices straight to the load, which by construction are
 // never below the bias).
-template <typename SrcT>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const SrcT* p, int count,
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t source_resource(const float* p, int count,
                                                                   unsigned bias) {
-  const uintptr_t base = reinterpret_cast<uintptr_t>(p) - uintptr_t(bias) * sizeof(SrcT);
-  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), short(sizeof(SrcT)),
+  const uintptr_t base = reinterpret_cast<uintptr_t>(p) - uintptr_t(bias) * sizeof(float);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), short(sizeof(float)),
                                            count + int(bias), kBufferWord3);
 }
 
 // Element `at` of the source map.
-template <typename SrcT>
-__device__ __forceinline__ float load_src(__amdgpu_buffer_rsrc_t r, unsigned at);
-template <>
-__device__ __forceinline__ float load_src<float>(__amdgpu_buffer_rsrc_t r, unsigned at) {
+__device__ __forceinline__ float load_src(__amdgpu_buffer_rsrc_t r, unsigned at) {
   return rrt_struct_load_f32(r, int(at), 0, 0, 0);
-}
-template <>
-__device__ __forceinline__ float load_src<__half>(__amdgpu_buffer_rsrc_t r, unsigned at) {
-  return __half2float(__short_as_half(rrt_struct_load_i16(r, int(at), 0, 0, 0)));
 }
 
 // Code e of a packed 11-bit row (RRT_S11): bits [11 e, 11 e + 11) of the
@@ -193,7 +182,7 @@ __device__ __forceinline__ void tile_levels_d(double a, double b, double c, doub
 }
 
 struct RelightParams {
-  const void* src;
+  const float* src;       // source map (binary32)
   const float* vrot;
   const float* frot;
   const int32_t* tidx;
@@ -308,7 +297,7 @@ __device__ __forceinline__ unsigned latlong_source_h(const LLTab& t, int i, int 
 
 // A lane's T x T gathered texels of block (by, bx) of square `face` through
 // the longitude-latitude rule at H = 2^LOGH.
-template <int LOGH, int Q, int TS, int T, typename SrcT>
+template <int LOGH, int Q, int TS, int T>
 __device__ __forceinline__ void latlong_gather(float (&val)[T][T], const LLTab& tab,
                                                __amdgpu_buffer_rsrc_t src, int face, int by,
                                                int bx, int ty, int tx, float cb, float sb, int sa,
@@ -320,7 +309,7 @@ __device__ __forceinline__ void latlong_gather(float (&val)[T][T], const LLTab& 
     for (int b = 0; b < T; ++b) {
       const int i = by * Q + TS * a + ty;
       const int jc = (face * n + bx * Q + TS * b + tx + sc) & (2 * n - 1);
-      val[a][b] = load_src<SrcT>(src, latlong_source_h<LOGH>(tab, i, jc, cb, sb, sa));
+      val[a][b] = load_src(src, latlong_source_h<LOGH>(tab, i, jc, cb, sb, sa));
     }
 }
 
@@ -550,7 +539,7 @@ __device__ __forceinline__ int classify(int idx, int logn, int G, unsigned faces
 // spilled): 0.430 -> 0.411 ms on the benchmark launch against 4 waves
 // unspilled; the lat-long variant held to 6 waves spills more and runs
 // slower, so it keeps its 5.
-template <int Q, typename SrcT, bool CHAIN, bool BRDF, bool LL>
+template <int Q, bool CHAIN, bool BRDF, bool LL>
 __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(RelightParams p) {
   constexpr int NF = LL ? 2 : 6;  // faces (squares) of the map
   // Blocks holding no listed entry of their own only feed the levels above
@@ -579,7 +568,7 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
   // the cube map's source map is in strips of four rows for n >= 4 (Q >= 4)
   constexpr bool STRIPS = Q >= 4 && !LL;
   const __amdgpu_buffer_rsrc_t src = source_resource(
-      static_cast<const SrcT*>(p.src), NF * (n << logn),
+      p.src, NF * (n << logn),
       LL ? 0u : (STRIPS ? strip_bias(logn) : texel_bias(logn)));
   const bool comp = p.comp != 0;
 
@@ -733,13 +722,13 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
                 float val[T][T];
                 // H below 32 has Q = H; from 32 on, Q = 32 and H = 32 .. 512
                 if constexpr (Q < 32) {
-                  latlong_gather<LOGQ, Q, TS, T, SrcT>(val, tab, src, face, by, bx, ty, tx, llcb,
+                  latlong_gather<LOGQ, Q, TS, T>(val, tab, src, face, by, bx, ty, tx, llcb,
                                                        llsb, llsa, llsc);
                 } else {
                   switch (logn) {
 #define RRT_LL_CASE(L)                                                                         \
   case L:                                                                                      \
-    latlong_gather<L, Q, TS, T, SrcT>(val, tab, src, face, by, bx, ty, tx, llcb, llsb, llsa, \
+    latlong_gather<L, Q, TS, T>(val, tab, src, face, by, bx, ty, tx, llcb, llsb, llsa, \
                                       llsc);                                                   \
     break;
                     RRT_LL_CASE(5)
@@ -755,7 +744,7 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
                         for (int b = 0; b < T; ++b) {
                           const int i = by * Q + TS * a + ty;
                           const int jc = (face * n + bx * Q + TS * b + tx + llsc) & (2 * n - 1);
-                          val[a][b] = load_src<SrcT>(
+                          val[a][b] = load_src(
                               src, latlong_source(tab, i, jc, llcb, llsb, logn, llsa));
                         }
                   }
@@ -833,7 +822,7 @@ __global__ __launch_bounds__(kThreads, CHAIN ? 5 : 1) void relight_kernel(Religh
                 float3 d = rw;
 #pragma unroll
                 for (int b = 0; b < T; ++b) {
-                  val[a][b] = load_src<SrcT>(
+                  val[a][b] = load_src(
                       src, STRIPS ? source_texel_strip(d.x, d.y, d.z, logn)
                              : source_texel_biased(d.x, d.y, d.z, logn));
                   d = dir_add(ax.mU, float(2 * TS), d);
@@ -993,8 +982,7 @@ __global__ void scatter_light(const int32_t* __restrict__ idx, const void* __res
 
 // Orthonormal (S, H, V, D) of every 2x2 block of the source map, for the
 // chain-rule rotation: blocks[face][bi][bj].
-template <typename SrcT>
-__global__ void source_blocks_kernel(const SrcT* __restrict__ src, int logn,
+__global__ void source_blocks_kernel(const float* __restrict__ src, int logn,
                                      float4* __restrict__ blocks) {
   const int hl = logn - 1;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1003,8 +991,8 @@ __global__ void source_blocks_kernel(const SrcT* __restrict__ src, int logn,
   // the source map is in strips of four rows (n >= 32 here): the block's
   // two rows share a strip, its columns are four elements apart
   const unsigned at = strip_offset(unsigned((f << logn) + 2 * bi), unsigned(2 * bj), logn);
-  const float a = float(src[at]), b = float(src[at + 4]);
-  const float c = float(src[at + 1]), d = float(src[at + 5]);
+  const float a = src[at], b = src[at + 4];
+  const float c = src[at + 1], d = src[at + 5];
   blocks[q] = make_float4(0.5f * ((a + b) + (c + d)), 0.5f * ((a - b) + (c - d)),
                           0.5f * ((a + b) - (c + d)), 0.5f * ((a - b) - (c - d)));
 }
@@ -1144,7 +1132,7 @@ __global__ void rotate_pixels(const float* __restrict__ src, const float* __rest
   dst[int64_t(r) * 6 * per_face + q] = src[min(at, unsigned(6 * per_face - 1))];
 }
 
-template <int Q, typename SrcT, bool CHAIN = false, bool BRDF = false, bool LL = false>
+template <int Q, bool CHAIN = false, bool BRDF = false, bool LL = false>
 int launch_q(const RelightParams& prm_in, int64_t nvert, hipStream_t s) {
   RelightParams prm = prm_in;
   const int G = (1 << prm.logn) / Q;
@@ -1154,39 +1142,36 @@ int launch_q(const RelightParams& prm_in, int64_t nvert, hipStream_t s) {
     prm.ll_tab_off = int(lds);
     lds += size_t(latlong_grid_floats(1 << prm.logn)) * 4;
   }
-  hipLaunchKernelGGL((relight_kernel<Q, SrcT, CHAIN, BRDF, LL>), dim3(unsigned(nvert)),
+  hipLaunchKernelGGL((relight_kernel<Q, CHAIN, BRDF, LL>), dim3(unsigned(nvert)),
                      dim3(kThreads), lds, s, prm);
   return check_launch("relight_kernel");
 }
 
-template <typename SrcT, bool BRDF>
+template <bool BRDF>
 int launch_size(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
   switch (n < kBlock ? n : kBlock) {
-    case 2: return launch_q<2, SrcT, false, BRDF>(prm, nvert, s);
-    case 4: return launch_q<4, SrcT, false, BRDF>(prm, nvert, s);
-    case 8: return launch_q<8, SrcT, false, BRDF>(prm, nvert, s);
-    case 16: return launch_q<16, SrcT, false, BRDF>(prm, nvert, s);
-    default: return launch_q<kBlock, SrcT, false, BRDF>(prm, nvert, s);
+    case 2: return launch_q<2, false, BRDF>(prm, nvert, s);
+    case 4: return launch_q<4, false, BRDF>(prm, nvert, s);
+    case 8: return launch_q<8, false, BRDF>(prm, nvert, s);
+    case 16: return launch_q<16, false, BRDF>(prm, nvert, s);
+    default: return launch_q<kBlock, false, BRDF>(prm, nvert, s);
   }
 }
 
-template <typename SrcT>
 int launch_latlong(const RelightParams& prm, int n, int64_t nvert, hipStream_t s) {
   switch (n < kBlock ? n : kBlock) {
-    case 4: return launch_q<4, SrcT, false, false, true>(prm, nvert, s);
-    case 8: return launch_q<8, SrcT, false, false, true>(prm, nvert, s);
-    case 16: return launch_q<16, SrcT, false, false, true>(prm, nvert, s);
-    default: return launch_q<kBlock, SrcT, false, false, true>(prm, nvert, s);
+    case 4: return launch_q<4, false, false, true>(prm, nvert, s);
+    case 8: return launch_q<8, false, false, true>(prm, nvert, s);
+    case 16: return launch_q<16, false, false, true>(prm, nvert, s);
+    default: return launch_q<kBlock, false, false, true>(prm, nvert, s);
   }
 }
 
-template <typename SrcT>
-int launch_src(const RelightParams& prm, int n, int64_t nvert, bool chain, bool latlong,
-               hipStream_t s) {
-  if (latlong) return launch_latlong<SrcT>(prm, n, nvert, s);
-  if (chain) return launch_q<kBlock, SrcT, true>(prm, nvert, s);
-  return prm.brdf ? launch_size<SrcT, true>(prm, n, nvert, s)
-                  : launch_size<SrcT, false>(prm, n, nvert, s);
+int launch_variant(const RelightParams& prm, int n, int64_t nvert, bool chain, bool latlong,
+                   hipStream_t s) {
+  if (latlong) return launch_latlong(prm, n, nvert, s);
+  if (chain) return launch_q<kBlock, true>(prm, nvert, s);
+  return prm.brdf ? launch_size<true>(prm, n, nvert, s) : launch_size<false>(prm, n, nvert, s);
 }
 
 }  // namespace
@@ -1225,8 +1210,7 @@ int launch_relight(const RelightLaunch& a, hipStream_t s) {
   p.ll_tab_off = 0;
   p.order = a.order;
   const bool chain = (a.flags & RRT_CHAIN_RULE) != 0;
-  return a.src_f16 ? launch_src<__half>(p, a.n, a.nvert, chain, a.latlong, s)
-                   : launch_src<float>(p, a.n, a.nvert, chain, a.latlong, s);
+  return launch_variant(p, a.n, a.nvert, chain, a.latlong, s);
 }
 
 int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, int n, int squares,
@@ -1240,17 +1224,10 @@ int launch_scatter_light(const int32_t* idx, const void* val, int dtype, int k, 
   return check_launch("scatter_light");
 }
 
-int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStream_t s) {
+int launch_source_blocks(const float* src, int n, float* blocks, hipStream_t s) {
   const int total = 6 * (n / 2) * (n / 2);
-  if (f16) {
-    hipLaunchKernelGGL(source_blocks_kernel<__half>, dim3(unsigned((total + 255) / 256)), dim3(256),
-                       0, s, static_cast<const __half*>(src), ilog2(n),
-                       reinterpret_cast<float4*>(blocks));
-  } else {
-    hipLaunchKernelGGL(source_blocks_kernel<float>, dim3(unsigned((total + 255) / 256)), dim3(256),
-                       0, s, static_cast<const float*>(src), ilog2(n),
-                       reinterpret_cast<float4*>(blocks));
-  }
+  hipLaunchKernelGGL(source_blocks_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s,
+                     src, ilog2(n), reinterpret_cast<float4*>(blocks));
   return check_launch("source_blocks");
 }
 

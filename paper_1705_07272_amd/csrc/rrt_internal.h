@@ -23,12 +23,13 @@ inline int ilog2(int64_t x) {
 }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float|half];
-// after prepare the staging area holds the chain rule's 6 (n/2)^2 float4 blocks.
+// Workspace of relight: [dense staging 6n^2 float][source map 6n^2 float]
+// (a binary32 map for either lighting dtype); after prepare the staging area
+// holds the chain rule's 6 (n/2)^2 float4 blocks.
 struct RelightWs {
   size_t dense_off, src_off, total;
 };
-RelightWs relight_ws(int n, bool f16);
+RelightWs relight_ws(int n);
 // Host-side validation of rrt_relight's descriptors and flags (abi.cpp); a
 // non-zero return has recorded the message for rrt_last_error().
 int validate_relight(const rrt_light* L, const rrt_rotations* R, const rrt_transport* T);
@@ -42,9 +43,6 @@ int launch_haar_forward(const float* pix, float* coef, int n, int64_t squares, h
 // row-major order
 int launch_haar_inverse(const float* coef, float* pix, int n, int64_t squares, hipStream_t s,
                         bool strips = false);
-// Inverse transform writing binary16 pixels (source map of the F16 form).
-int launch_haar_inverse_f16(const float* coef, __half* pix, float* staging, int n, int squares,
-                            hipStream_t s, bool strips = false);
 
 // Selection (topk.hip).
 size_t topk_workspace_bytes(int64_t rows, int64_t len, int k);
@@ -60,9 +58,8 @@ int launch_rotate_pixels(const float* src, const float* rot, int nrot, int n, fl
                          hipStream_t s);
 
 struct RelightLaunch {
-  const void* src;          // [6][n][n] float32 or binary16 source map, in strips of four rows
-                            // for n >= 4 (row-major for n < 4 and for the [2][n][n] lat-long map)
-  bool src_f16;
+  const float* src;         // [6][n][n] source map, in strips of four rows for n >= 4
+                            // (row-major for n < 4 and for the [2][n][n] lat-long map)
   const float* vert_rot;    // [V][9]
   const float* frame_rot;   // [F][9] or nullptr
   const int32_t* t_idx;     // [V][nnz] or nullptr (dense)
@@ -93,7 +90,7 @@ struct RelightLaunch {
 // sines, column cosines [2H], boundary cosines [H]; 7 H floats.
 inline int latlong_grid_floats(int H) { return 7 * H; }
 int launch_latlong_grid(int H, float* grid, hipStream_t s);
-int launch_source_blocks(const void* src, bool f16, int n, float* blocks, hipStream_t s);
+int launch_source_blocks(const float* src, int n, float* blocks, hipStream_t s);
 int launch_coarsen_indices(const int32_t* idx, int64_t count, int n, int levels, int32_t* out,
                            hipStream_t s);
 int launch_relight(const RelightLaunch& a, hipStream_t s);
