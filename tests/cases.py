@@ -185,3 +185,26 @@ def rows_and_reference(w, vids, li, lv, rot, frot, workers=8, frames=None):
     ref = np.concatenate([p[2] for p in parts], axis=1)
     mag = np.concatenate([p[3] for p in parts], axis=1)
     return idx, val, ref, mag
+
+
+def chain_reference(case):
+    """The checker's chain-rule radiance [F, V] and its magnitude scale
+    sum_k |T_k ghat_k| (FP64)."""
+    from oracle.chain import chain_rotate
+    from oracle.haar import haar_forward
+    from oracle.relight import frame_vertex_rotation, reconstruct_lighting
+    n = case["n"]
+    P = reconstruct_lighting(case["light_idx"], case["light_val"], n)
+    V = case["vert_rot"].shape[0]
+    F = 1 if case["frame_rot"] is None else case["frame_rot"].shape[0]
+    ref = np.zeros((F, V))
+    scale = np.zeros((F, V))
+    for v in range(V):
+        idx = case["t_idx"][v].astype(np.int64)
+        tv = case["t_val"][v].astype(np.float64)
+        for f in range(F):
+            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], v, f, n)
+            g = haar_forward(chain_rotate(P, Rq)).ravel()[idx]
+            ref[f, v] = np.dot(tv, g)
+            scale[f, v] = np.abs(tv * g).sum()
+    return ref, scale

@@ -226,9 +226,9 @@ def _full_launch_rows(rrt, w, sample):
 def test_full_cube128_v50000_chain_rule(rrt):
     """The benchmark launch with the chain-rule phase shift (row f1): 96
     sampled outputs of the full launch against the checker's chain-rule
-    rotation on the same stored inputs, rel-L2 <= 1e-5."""
-    from cases import frame_errors
-    from oracle.chain import relight_chain
+    rotation on the same stored inputs, every element within the FP32
+    element bound, rel-L2 <= 1e-5."""
+    from cases import chain_reference, frame_errors
     from scenes.scene import WORKLOADS, vertex_rotations
     w = WORKLOADS[2]
     sample = _sample(w.nverts, 96, 5)
@@ -237,9 +237,11 @@ def test_full_cube128_v50000_chain_rule(rrt):
                       torch.from_numpy(case["light_val"]).cuda(),
                       torch.from_numpy(vertex_rotations(w)).cuda(), idx, val, chain_rule=True)
     torch.cuda.synchronize()
-    ref = relight_chain(case["light_idx"], case["light_val"], w.n, case["vert_rot"], None,
-                        case["t_idx"], case["t_val"])
-    err = max(frame_errors(out.cpu().numpy()[:, sample], ref))
+    ref, mag = chain_reference(case)
+    got = out.cpu().numpy()[:, sample].astype(np.float64)
+    bound = 1e-5 * np.abs(ref) + 2e-7 * mag
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
+    err = max(frame_errors(got, ref))
     print(f"cube128 V=50000 chain rule: sampled rel-L2 {err:.3e}")
     assert err <= 1e-5
 

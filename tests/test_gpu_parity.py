@@ -469,27 +469,7 @@ def test_relight_from_coarser_level(rrt, n, levels, frames):
 
 
 # ---------------------------------------------------------------- chain rule (f1)
-def chain_reference(case):
-    """The checker's chain-rule radiance [F, V] and its magnitude scale
-    sum_k |T_k ghat_k| (FP64)."""
-    from oracle.chain import chain_rotate
-    from oracle.haar import haar_forward
-    from oracle.relight import frame_vertex_rotation, reconstruct_lighting
-    n = case["n"]
-    P = reconstruct_lighting(case["light_idx"], case["light_val"], n)
-    V = case["vert_rot"].shape[0]
-    F = 1 if case["frame_rot"] is None else case["frame_rot"].shape[0]
-    ref = np.zeros((F, V))
-    scale = np.zeros((F, V))
-    for v in range(V):
-        idx = case["t_idx"][v].astype(np.int64)
-        tv = case["t_val"][v].astype(np.float64)
-        for f in range(F):
-            Rq = frame_vertex_rotation(case["vert_rot"], case["frame_rot"], v, f, n)
-            g = haar_forward(chain_rotate(P, Rq)).ravel()[idx]
-            ref[f, v] = np.dot(tv, g)
-            scale[f, v] = np.abs(tv * g).sum()
-    return ref, scale
+from cases import chain_reference  # noqa: E402  (the checker's chain rule with its scale)
 
 
 @pytest.mark.parametrize("n,nframes,compensated", [(32, 1, False), (64, 3, True), (128, 1, False)])
